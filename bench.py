@@ -1,0 +1,194 @@
+"""Benchmark of the boosted-frame EM-PIC step on one MI355X.
+
+Default workload: the large 3D3V boosted-frame laser-wakefield box,
+512(z) x 256(x) x 256(y) cells, 16 electrons per cell (537M electrons in the
+box), gamma_boost 30, a0 2, split FP32 positions with the FP64 gamma solve.
+One step = injection/sort (every 20 steps, amortised), the fused particle
+kernel (gather, modified-Lorentz push, move, charge-conserving deposit) and
+the Yee update.  Synthetic inputs of the paper's LWFA shape (no dataset).
+
+Prints one JSON line: particle-steps/s of the split-precision path (value),
+the plain FP64 path on the same workload and the speedup, serving latency
+p50/p99 for a Poisson stream of 2D runs, the roofline fraction of the
+particle kernel measured with HIP events, and the CPU oracle timed on a
+bounded sample on this host.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "particle-steps/s (full PIC step) FP32 vs FP64 + p50/p99 batched-run latency"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg: str):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(n_particles: float, n_cells: float, dims: int, rsz: int):
+    """Algorithmic HBM bytes per step.  Particle kernel: read + write of the
+    particle state (int32 cell, offsets, momenta) plus the gather read of
+    E and B and the current write per cell; field kernel: read E, B, J and
+    write E, B per cell."""
+    part = (4 + dims * rsz + 3 * rsz) * 2
+    return {
+        "particle_kernel": n_particles * part + n_cells * 9 * rsz,
+        "field_kernel": n_cells * 15 * rsz,
+        "per_particle": part,
+    }
+
+
+def run_main(cfg, precision, steps, warmup, pic, torch):
+    run = pic.Run(cfg, precision)
+    d0 = run.diag(pic.PIC_DIAG_PARTICLES)
+    log(f"[{precision}] init done: {d0['n_particles']} electrons in the box, "
+        f"{run.nbytes / 2**30:.1f} GiB state")
+    run.step(warmup)
+    run.synchronize()
+    t0 = time.perf_counter()
+    run.step(steps)
+    run.synchronize()
+    t1 = time.perf_counter()
+    d1 = run.diag(pic.PIC_DIAG_ALL)
+    n_box = 0.5 * (d0["n_particles"] + d1["n_particles"])
+    sec = t1 - t0
+    out = {"ms_per_step": 1e3 * sec / steps, "value": n_box * steps / sec, "n_box": n_box,
+           "diag": {k: d1[k] for k in ("step", "U_E", "U_B", "Ez_max", "KE", "n_particles",
+                                       "gauss_drift", "err_bits")}}
+    log(f"[{precision}] {out['ms_per_step']:.3f} ms/step, {out['value']:.3e} particle-steps/s")
+    return run, out
+
+
+def kernel_roofline(run, pic, nsteps):
+    ms = pic.pic_step_timed(run.handle, nsteps)
+    slots, live = pic.pic_particle_count(run.handle)
+    ncell = run.npts
+    rsz = 8 if run.params.precision == pic.PIC_FP64 else 4
+    b = algorithmic_bytes(live, ncell, run.params.dims, rsz)
+    ach = b["particle_kernel"] / (ms["particles"] * 1e-3) / 1e9
+    achf = b["field_kernel"] / (ms["fields"] * 1e-3) / 1e9
+    return ms, {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": ach / HBM_PEAK_GBS, "traffic": None,
+                "kernel": "k_particles (gather+push+move+deposit)",
+                "algorithmic_bytes_per_launch": b["particle_kernel"],
+                "bytes_per_particle": b["per_particle"], "particles_per_launch": live,
+                "ms_per_launch": ms["particles"],
+                "field_kernel": {"achieved": achf, "frac": achf / HBM_PEAK_GBS,
+                                 "ms_per_launch": ms["fields"]},
+                "sort_ms_per_step": ms["sort"], "step_ms_events": ms["step"]}
+
+
+def serving(pic, torch, n_requests, budget_gib, chunk):
+    from paper_0909_5603_amd import serve, workloads
+
+    reqs = workloads.serving_stream(n_requests, seed=5)
+    res = serve.serve_stream(reqs, budget_bytes=int(budget_gib * 2**30), chunk_steps=chunk)
+    return res
+
+
+def cpu_baseline(seconds_target=15.0):
+    import oracle
+    from paper_0909_5603_amd import workloads
+
+    cfg = workloads.scaled_3d(64, 32, 32, 16)
+    st = oracle.State(cfg)
+    n_box = st.diag()["n_particles"]
+    st.step(1)
+    t0 = time.perf_counter()
+    steps = 0
+    while True:
+        st.step(1)
+        steps += 1
+        if time.perf_counter() - t0 > seconds_target or steps >= 20:
+            break
+    sec = time.perf_counter() - t0
+    st.close()
+    return {"value": n_box * steps / sec, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"FP64 C oracle, one thread, 3D box 64x32x32 with every other parameter of the "
+                      f"512x256x256 workload (16 ppc, {n_box} electrons in the box), {steps} steps, "
+                      f"{sec:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="c5", choices=["c5", "c3"])
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--timing-steps", type=int, default=20)
+    ap.add_argument("--serve-requests", type=int, default=64)
+    ap.add_argument("--profile", action="store_true",
+                    help="only the split-precision timed loop (for rocprofv3 runs)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(see the sharding paragraph in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_0909_5603_amd import pic, workloads
+
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    pic.lib()
+    cfg = workloads.config(args.workload)
+    line = {"metric": METRIC, "unit": "particle-steps/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32", "data": "synthetic"}
+    run, r32 = run_main(cfg, "fp32", args.steps, args.warmup, pic, torch)
+    line["value"] = r32["value"]
+    line["ms_per_step"] = r32["ms_per_step"]
+    line["config"] = {
+        "workload": (f"3D3V boosted-frame LWFA {cfg['nz']}x{cfg['nx']}x{cfg['ny']} cells, "
+                     f"{cfg['ppc']} e-/cell, gamma_boost {cfg['gamma_boost']}, a0 {cfg['a0']}, "
+                     f"sort every {cfg['sort_every']} steps; split FP32 positions, FP64 gamma solve"),
+        "particles_in_box": r32["n_box"], "cells": cfg["nz"] * cfg["nx"] * cfg["ny"],
+        "parallelism": "single GPU",
+    }
+    ms, roof = kernel_roofline(run, pic, args.timing_steps)
+    line["roofline"] = roof
+    line["diag_fp32"] = r32["diag"]
+    log(f"[fp32] stage ms/step: {ms}; particle kernel {roof['achieved']:.0f} GB/s "
+        f"({100 * roof['frac']:.1f}% of HBM peak)")
+    run.close()
+    del run
+    torch.cuda.empty_cache()
+    if args.profile:
+        print(json.dumps(line), flush=True)
+        return
+    if not args.no_fp64:
+        run64, r64 = run_main(cfg, "fp64", max(args.steps // 2, 10), max(args.warmup // 2, 2), pic, torch)
+        ms64, roof64 = kernel_roofline(run64, pic, max(args.timing_steps // 2, 4))
+        line["fp64"] = {"value": r64["value"], "ms_per_step": r64["ms_per_step"],
+                        "roofline_particle_kernel": {k: roof64[k] for k in ("achieved", "frac", "ms_per_launch")}}
+        line["speedup_fp32_vs_fp64"] = r32["value"] / r64["value"]
+        run64.close()
+        del run64
+        torch.cuda.empty_cache()
+    if not args.no_serving:
+        res = serving(pic, torch, args.serve_requests, budget_gib=96.0, chunk=25)
+        line["serving"] = res
+        log(f"[serving] p50 {res['p50_ms']:.1f} ms, p99 {res['p99_ms']:.1f} ms, "
+            f"{res['throughput']:.3e} particle-steps/s")
+    if not args.no_cpu:
+        cb = cpu_baseline()
+        line["cpu_baseline"] = cb
+        log(f"[cpu] oracle {cb['value']:.3e} particle-steps/s")
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,202 @@
+/*
+ * libpic: one-GPU (MI355X, gfx950) boosted-frame electromagnetic
+ * particle-in-cell step, after Vay, Fawley, Geddes, Cormier-Michel and Grote,
+ * "Speeding up simulations of relativistic systems using an optimal boosted
+ * frame" (2009).
+ *
+ * The calls follow the paper's statement of the problem (Sec. 2): inputs are
+ * given in the laboratory frame (laser and plasma parameters, second
+ * paragraph), the system is evolved by the relativistic PIC algorithm in the
+ * boosted frame (third paragraph), and diagnostics are reported from the
+ * boosted-frame state (plus the boost-invariant longitudinal field).
+ *
+ * Ownership.  The caller owns all device memory: it allocates one buffer of
+ * pic_state_bytes() bytes and passes it to pic_init_boosted(), together with
+ * the HIP stream everything is enqueued on.  The library never allocates
+ * device memory; it owns only the small host-side handle and any HIP graphs
+ * it captures.  The buffer must stay alive and untouched until pic_free().
+ *
+ * Errors.  No call throws.  Argument errors are returned synchronously as a
+ * negative pic_status and described by pic_last_error() (thread-local).
+ * Errors raised inside kernels (non-finite momentum, particle capacity
+ * exceeded) set bits in a device error word; pic_diag() reports them and
+ * returns PIC_ESTATE.
+ *
+ * Units: lengths in c/omega_p and times in 1/omega_p of the laboratory plasma
+ * frequency; c = eps0 = 1; electron charge -1 and mass 1.
+ */
+#ifndef PIC_H
+#define PIC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PIC_OK = 0,
+  PIC_EINVAL = -1,    /* bad argument */
+  PIC_EBUDGET = -2,   /* device buffer smaller than pic_state_bytes() */
+  PIC_EHIP = -3,      /* a HIP runtime call failed */
+  PIC_ECFL = -4,      /* time step violates the CFL bound */
+  PIC_ENAN = -5,      /* a kernel produced a non-finite momentum */
+  PIC_ECAPACITY = -6, /* particle storage overflowed */
+  PIC_ESTATE = -7     /* the run carries a device-side error */
+} pic_status;
+
+enum { PIC_BC_OPEN = 0, PIC_BC_PERIODIC = 1 };
+enum { PIC_VAY = 0, PIC_BORIS = 1 };
+enum { PIC_FP32_SPLIT = 0, PIC_FP64 = 1 };
+
+/* device error-word bits */
+enum { PIC_ERR_NAN = 1u, PIC_ERR_CAPACITY = 2u, PIC_ERR_CELL = 4u };
+
+/* pic_lab_params.diag_flags */
+enum {
+  PIC_DIAGF_CONTINUITY = 1u /* measure the continuity residual every step */
+};
+
+/* Laboratory-frame problem description (Sec. 2, second paragraph: laser and
+ * plasma parameters are given in the laboratory and transformed). */
+typedef struct {
+  int dims;              /* 2: (z,x) with three velocity components; 3: (z,x,y) */
+  int nz, nx, ny;        /* boosted-frame cells; ny ignored in 2D.  nx, ny must be
+                            multiples of the transverse tile (2D: 16; 3D: 8 x 4) */
+  double dz, dx, dy;     /* cell sizes in c/omega_p */
+  double cfl;            /* dt = cfl / sqrt(sum_d 1/d^2); must be in (0, 1) */
+  int ppc;               /* electrons per cell (>= 0) */
+  uint64_t seed;         /* Philox4x64-10 key for positions and thermal momenta */
+  double gamma_boost;    /* Lorentz factor of the boosted frame (>= 1) */
+  double n_lab_cm3;      /* laboratory plasma density; sets omega_p */
+  double u_th;           /* laboratory thermal momentum spread per component */
+  double a0;             /* laser normalised amplitude (0: no laser) */
+  double lambda0_um;     /* laser wavelength, laboratory frame */
+  double waist;          /* transverse 1/e field radius, c/omega_p */
+  double tau_lab;        /* lab envelope e-fold length; <= 0: boosted length nz dz/8 */
+  int pol_axis;          /* 1 = x, 2 = y */
+  int bc_z;              /* PIC_BC_OPEN (Mur + plasma reservoir) or PIC_BC_PERIODIC */
+  int pusher;            /* PIC_VAY (default) or PIC_BORIS */
+  int precision;         /* PIC_FP32_SPLIT or PIC_FP64 */
+  int sort_every;        /* tile sort and plasma-column injection cadence (>= 1) */
+  unsigned diag_flags;   /* PIC_DIAGF_* */
+} pic_lab_params;
+
+typedef struct pic_run pic_run; /* opaque host handle */
+
+/* Diagnostics of the boosted-frame state at step `step` (a8).  Energies and
+ * maxima are taken over interior points: two cells are excluded at each open
+ * z end. */
+typedef struct {
+  int64_t step;
+  double t;
+  double U_E, U_B;       /* 1/2 sum F^2 dV */
+  double Ez_max;         /* max |E_z| (wake amplitude; invariant under the z boost) */
+  double KE;             /* sum w (gamma - 1) over interior electrons */
+  int64_t n_particles;   /* electrons inside the physical box */
+  double cont_resid;     /* max over steps since the last call of
+                            max|rho^{n+1}-rho^n+dt div J| / max|rho_e^n|
+                            (needs PIC_DIAGF_CONTINUITY, else -1) */
+  double gauss_drift;    /* max |(divE-rho)^n-(divE-rho)^0| / max|rho_e^0| */
+  uint32_t err_bits;     /* device error word */
+} pic_diag_out;
+
+enum { PIC_DIAG_FIELDS = 1u, PIC_DIAG_PARTICLES = 2u, PIC_DIAG_GAUSS = 4u, PIC_DIAG_ALL = 7u };
+
+/* Bytes of device memory a run of these parameters needs.  Pure host
+ * function; used for admission by memory budget.  Returns PIC_EINVAL for
+ * invalid parameters. */
+pic_status pic_state_bytes(const pic_lab_params* p, size_t* bytes);
+
+/* Transform the laboratory inputs to the boosted frame and lay out the run in
+ * dev_buf (Sec. 2, second paragraph: Doppler-shifted laser, denser drifting
+ * plasma).  Enqueues the laser transform, plasma creation and the first tile
+ * sort on `hip_stream` (a hipStream_t; NULL means the null stream) and
+ * returns at once.  dev_buf: device pointer to >= pic_state_bytes() bytes,
+ * owned by the caller. */
+pic_status pic_init_boosted(const pic_lab_params* p, void* dev_buf, size_t bytes,
+                            void* hip_stream, pic_run** out);
+
+/* Enqueue nsteps full PIC steps (gather, modified-Lorentz push, move,
+ * charge-conserving deposit, Yee update; sort and injection every sort_every
+ * steps).  Asynchronous. */
+pic_status pic_step(pic_run* run, int nsteps);
+
+/* Advance several runs together: their tiles share the same kernel launches.
+ * All runs must have the same dims and precision and share one stream (the
+ * first run's).  nsteps[i] may differ; runs drop out when done. */
+pic_status pic_step_batch(pic_run* const* runs, const int* nsteps, int n);
+
+/* Enqueue nsteps steps without graph replay, bracketing each stage with HIP
+ * events recorded on the run's stream, synchronise, and return the mean
+ * device time per step of each stage in milliseconds: ms[0] = injection and
+ * tile sort, ms[1] = particle kernel (gather, push, move, deposit),
+ * ms[2] = field kernel and step advance, ms[3] = the whole step.
+ * For measurement; the state advances exactly as with pic_step. */
+pic_status pic_step_timed(pic_run* run, int nsteps, double ms[4]);
+
+/* Compute diagnostics (what = PIC_DIAG_* mask); synchronises the run's
+ * stream.  Returns PIC_ESTATE if the device error word is set. */
+pic_status pic_diag(pic_run* run, unsigned what, pic_diag_out* out);
+
+/* Number of particle slots in storage order (live and dead) and of live ones. */
+pic_status pic_particle_count(pic_run* run, int64_t* slots, int64_t* live);
+
+/* Copy live particles of storage slots [first, first+count) to host arrays
+ * (absolute positions in c/omega_p, momenta u = gamma v, lattice ids).
+ * Arrays must hold `count` entries; *n_out receives the number written.
+ * Synchronises the run's stream. */
+pic_status pic_read_particles(pic_run* run, int64_t first, int64_t count,
+                              double* z, double* x, double* y,
+                              double* ux, double* uy, double* uz, uint32_t* id,
+                              int64_t* n_out);
+
+/* Field component ids for pic_read_fields */
+enum { PIC_F_EX = 0, PIC_F_EY, PIC_F_EZ, PIC_F_BX, PIC_F_BY, PIC_F_BZ,
+       PIC_F_JX_LAST, PIC_F_JY_LAST, PIC_F_JZ_LAST };
+
+/* Copy one field component at integer time n (B is advanced to integer
+ * time on the fly) as doubles, layout [ny][nx][nzf] with z fastest,
+ * nzf = nz+1 (open z) or nz (periodic).  The J_LAST components are the
+ * current of the most recent step (only with PIC_DIAGF_CONTINUITY).
+ * host must hold `npts` doubles.  Synchronises. */
+pic_status pic_read_fields(pic_run* run, int comp, double* host, int64_t npts);
+
+/* Boosted-frame quantities derived from the parameters. */
+typedef struct {
+  double dt, beta_b, gamma_b, dminus, dplus, skin_um, k0_lab, E0_lab;
+  double L_lab, L_boost, zc_boost, weight, dV;
+  int reservoir, nzf;
+  int64_t capacity; /* particle slots per buffer */
+  int ntiles;
+} pic_derived;
+pic_status pic_get_derived(const pic_run* run, pic_derived* out);
+
+/* Options for pic_set_option */
+enum { PIC_OPT_GRAPH = 1 /* 1 (default): replay each step as a captured HIP graph */ };
+pic_status pic_set_option(pic_run* run, int opt, int value);
+
+/* Release the host handle and graphs (device memory stays the caller's).
+ * NULL-safe. */
+pic_status pic_free(pic_run* run);
+
+/* Message for the last error on this thread ("" if none). */
+const char* pic_last_error(void);
+
+/* Pusher microbenchmark (Sec. 2, first paragraph: the modified Lorentz-force
+ * pusher against the Boris pusher).  n particles, each in its own uniform
+ * field E = (Ex[p], 0, 0) and the common B, advanced nsteps steps of dt with
+ * positions kept as an int32 cell plus an offset in [0,1) on a unit grid.
+ * All arrays are caller-owned device memory, SoA:
+ *   Ex[n]; u[3n] = ux|uy|uz; cell[3n] = cx|cy|cz; off[3n] = ox|oy|oz,
+ * of float (PIC_FP32_SPLIT; the gamma solve still runs in FP64) or double
+ * (PIC_FP64).  One kernel launch per step on hip_stream; asynchronous. */
+pic_status pic_push_bench(int precision, int pusher, int64_t n, int nsteps, double dt,
+                          const double B[3], void* Ex, void* u, int32_t* cell, void* off,
+                          void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,447 @@
+// Initial boosted-frame fields and the diagnostics kernels.
+//
+// Laser (Sec. 2, second paragraph: laser parameters are given in the
+// laboratory and the waves are Doppler shifted in the boosted frame): every
+// Yee point (z', x, y) of the boosted grid at t' = 0 corresponds to the
+// laboratory event z = gamma_b z', t = gamma_b beta_b z'.  The laboratory
+// pulse (flat phase fronts, Gaussian transverse profile and envelope, B =
+// z x E) is evaluated there in FP64 and the fields are boosted with the
+// Lorentz field transformation, then stored in the run's precision.  B is
+// then moved back half a step to B^{-1/2}, the leapfrog state.
+//
+// Diagnostics run outside the step loop and accumulate in FP64.
+#include <hip/hip_runtime.h>
+
+#include "launch.hpp"
+#include "pic_dev.hpp"
+
+namespace pic {
+
+// ------------------------------------------------------------------ laser
+template <typename R>
+__global__ void k_laser(const RunDev* __restrict__ rdp) {
+  const RunDev& rd = *rdp;
+  const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= rd.npts) return;
+  const int k = (int)(q % rd.nzf);
+  const long long t = q / rd.nzf;
+  const int i = (int)(t % rd.nx), j = (int)(t / rd.nx);
+  const double gb = rd.gamma_b, bb = rd.beta_b;
+  const double Lx = rd.nx * rd.dx, Ly = rd.ny * rd.dy;
+  for (int c = 0; c < 6; ++c) {
+    const int kmax = rd.open ? (stag(c, 0) ? rd.nz : rd.nz + 1) : rd.nz;
+    R val = R(0);
+    if (k < kmax) {
+      const double zp = (k + 0.5 * stag(c, 0)) * rd.dz;
+      const double x = (i + 0.5 * stag(c, 1)) * rd.dx;
+      const double y = rd.dims == 3 ? (j + 0.5 * stag(c, 2)) * rd.dy : 0.0;
+      // laboratory event of the boosted point at t' = 0
+      const double zl = gb * zp, tl = gb * bb * zp;
+      const double zeta = zl - rd.dminus * rd.zc_boost - tl;
+      double r2 = (x - 0.5 * Lx) * (x - 0.5 * Lx);
+      if (rd.dims == 3) r2 += (y - 0.5 * Ly) * (y - 0.5 * Ly);
+      const double amp = rd.E0_lab * exp(-r2 / (rd.waist * rd.waist)) *
+                         exp(-zeta * zeta / (rd.L_lab * rd.L_lab)) * cos(rd.k0_lab * zeta);
+      double E[3] = {0, 0, 0}, B[3] = {0, 0, 0};
+      if (rd.pol_axis == 1) {
+        E[0] = amp;
+        B[1] = amp;
+      } else {
+        E[1] = amp;
+        B[0] = -amp;
+      }
+      // field boost along +z
+      double v;
+      switch (c) {
+        case 0: v = gb * (E[0] - bb * B[1]); break;
+        case 1: v = gb * (E[1] + bb * B[0]); break;
+        case 2: v = E[2]; break;
+        case 3: v = gb * (B[0] + bb * E[1]); break;
+        case 4: v = gb * (B[1] - bb * E[0]); break;
+        default: v = B[2]; break;
+      }
+      val = R(v);
+    }
+    if (c < 3)
+      fptr<R>(rd.E[0][c])[q] = val;
+    else
+      fptr<R>(rd.B[0][c - 3])[q] = val;
+  }
+}
+
+// E value at integer index with the open/periodic z rules
+template <typename R>
+__device__ __forceinline__ double ev(const RunDev& rd, R* const* E, int c, int k, int i, int j) {
+  i = wrapi(i, rd.nx);
+  j = rd.dims == 3 ? wrapi(j, rd.ny) : 0;
+  if (rd.open) {
+    if (k < 0 || k >= zcount(rd, c)) return 0.0;
+  } else {
+    k = wrapi(k, rd.nz);
+  }
+  return (double)E[c][gidx(rd, k, i, j)];
+}
+
+// curl of E at the B point of component c (0,1,2 = x,y,z)
+template <typename R>
+__device__ __forceinline__ double curl_e(const RunDev& rd, R* const* E, int c, int k, int i, int j) {
+  const double idz = 1.0 / rd.dz, idx = 1.0 / rd.dx, idy = rd.dims == 3 ? 1.0 / rd.dy : 0.0;
+  if (c == 0)
+    return (ev(rd, E, 2, k, i, j + 1) - ev(rd, E, 2, k, i, j)) * idy -
+           (ev(rd, E, 1, k + 1, i, j) - ev(rd, E, 1, k, i, j)) * idz;
+  if (c == 1)
+    return (ev(rd, E, 0, k + 1, i, j) - ev(rd, E, 0, k, i, j)) * idz -
+           (ev(rd, E, 2, k, i + 1, j) - ev(rd, E, 2, k, i, j)) * idx;
+  return (ev(rd, E, 1, k, i + 1, j) - ev(rd, E, 1, k, i, j)) * idx -
+         (ev(rd, E, 0, k, i, j + 1) - ev(rd, E, 0, k, i, j)) * idy;
+}
+
+// B^{n+s dt} from B at the stored time: out = B + coef * curl E (valid points)
+template <typename R>
+__global__ void k_bshift(const RunDev* __restrict__ rdp, int src, int dst, double coef) {
+  const RunDev& rd = *rdp;
+  const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= rd.npts) return;
+  const int k = (int)(q % rd.nzf);
+  const long long t = q / rd.nzf;
+  const int i = (int)(t % rd.nx), j = (int)(t / rd.nx);
+  const int fb = rd.ctr->fbuf;
+  R* const* E = reinterpret_cast<R* const*>(rd.E[fb]);
+  const int bs = src < 0 ? fb : src, bd = dst < 0 ? (fb ^ 1) : dst;
+  for (int c = 0; c < 3; ++c) {
+    const bool valid = !rd.open || k < zcount(rd, 3 + c);
+    double v = 0.0;
+    if (valid) v = (double)fptr<R>(rd.B[bs][c])[q] + coef * curl_e(rd, E, c, k, i, j);
+    fptr<R>(rd.B[bd][c])[q] = R(v);
+  }
+}
+
+void launch_init_fields(int dims, int prec, const RunDev* rd, long long npts, hipStream_t s) {
+  (void)dims;
+  const int B = 256;
+  const unsigned G = (unsigned)((npts + B - 1) / B);
+  if (prec) {
+    hipLaunchKernelGGL(k_laser<double>, dim3(G), dim3(B), 0, s, rd);
+  } else {
+    hipLaunchKernelGGL(k_laser<float>, dim3(G), dim3(B), 0, s, rd);
+  }
+}
+
+// ------------------------------------------------------------------ reductions
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m);
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v = fmax(v, __shfl_xor(v, m));
+  return v;
+}
+// block (256 threads) reductions; result valid in thread 0
+__device__ double block_sum(double v, double* sh) {
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0) r = sh[0] + sh[1] + sh[2] + sh[3];
+  __syncthreads();
+  return r;
+}
+__device__ double block_max(double v, double* sh) {
+  v = wave_max(v);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0) r = fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
+  __syncthreads();
+  return r;
+}
+
+__device__ __forceinline__ bool interior(const RunDev& rd, int comp, int k) {
+  if (!rd.open) return true;
+  const int hi = stag(comp, 0) ? rd.nz - 3 : rd.nz - 2;
+  return k >= 2 && k <= hi;
+}
+
+__global__ void k_fill(double* p, long long n, double v) {
+  for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < n;
+       q += (long long)gridDim.x * blockDim.x)
+    p[q] = v;
+}
+
+// ------------------------------------------------------------------ charge
+// electron charge density on nodes (linear shape), FP64 atomics.  With
+// use_snap, liveness is taken from the snapshot of the cells before the
+// step, so particles removed during the step still count at their new
+// position.
+template <int DIM, typename R>
+__global__ void k_rho(const RunDev* __restrict__ rdp, double* rho, int use_snap) {
+  const RunDev& rd = *rdp;
+  const Counters& c = *rd.ctr;
+  const int pb = c.pbuf;
+  const double qw = -rd.weight;
+  double dv = rd.dz * rd.dx * (DIM == 3 ? rd.dy : 1.0);
+  const double s = qw / dv;
+  for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < c.n_slots;
+       q += (long long)gridDim.x * blockDim.x) {
+    const int cc = rd.cell[pb][q];
+    const bool live = use_snap ? (rd.cell_snap[q] >= 0) : (cc >= 0);
+    if (!live) continue;
+    const int cu = cc & 0x7fffffff;
+    const int k = cell_k(cu), i = cell_i(cu), j = DIM == 3 ? cell_j(cu) : 0;
+    const double oz = (double)fptr<R>(rd.off[pb][0])[q];
+    const double ox = (double)fptr<R>(rd.off[pb][1])[q];
+    const double oy = DIM == 3 ? (double)fptr<R>(rd.off[pb][2])[q] : 0.0;
+    const double wz[2] = {1.0 - oz, oz}, wx[2] = {1.0 - ox, ox}, wy[2] = {1.0 - oy, oy};
+    for (int cy = 0; cy < (DIM == 3 ? 2 : 1); ++cy)
+      for (int cx = 0; cx < 2; ++cx)
+        for (int cz = 0; cz < 2; ++cz) {
+          int kk = k + cz;
+          const int ii = wrapi(i + cx, rd.nx), jj = DIM == 3 ? wrapi(j + cy, rd.ny) : 0;
+          if (rd.open) {
+            if (kk < 0 || kk > rd.nz) continue;
+          } else {
+            kk = wrapi(kk, rd.nz);
+          }
+          const double wgt = wz[cz] * wx[cx] * (DIM == 3 ? wy[cy] : 1.0);
+          atomicAdd(rho + gidx(rd, kk, ii, jj), s * wgt);
+        }
+  }
+}
+
+__global__ void k_snap(const RunDev* __restrict__ rdp) {
+  const RunDev& rd = *rdp;
+  const Counters& c = *rd.ctr;
+  for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < c.n_slots;
+       q += (long long)gridDim.x * blockDim.x)
+    rd.cell_snap[q] = rd.cell[c.pbuf][q];
+}
+
+// divergence at node (k,i,j) of a field staggered like E
+template <typename R>
+__device__ __forceinline__ double div_e(const RunDev& rd, R* const* F, int k, int i, int j) {
+  const double idz = 1.0 / rd.dz, idx = 1.0 / rd.dx, idy = rd.dims == 3 ? 1.0 / rd.dy : 0.0;
+  return (ev(rd, F, 0, k, i, j) - ev(rd, F, 0, k, i - 1, j)) * idx +
+         (ev(rd, F, 1, k, i, j) - ev(rd, F, 1, k, i, j - 1)) * idy +
+         (ev(rd, F, 2, k, i, j) - ev(rd, F, 2, k - 1, i, j)) * idz;
+}
+
+// continuity residual |rho_b - rho_a + dt div J| and |rho_a| maxima (interior nodes)
+template <typename R>
+__global__ __launch_bounds__(256) void k_cont(const RunDev* __restrict__ rdp) {
+  __shared__ double sh[4];
+  const RunDev& rd = *rdp;
+  R* const* J = reinterpret_cast<R* const*>(rd.J);
+  double res = 0.0, rmax = 0.0;
+  for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < rd.npts;
+       q += (long long)gridDim.x * blockDim.x) {
+    const int k = (int)(q % rd.nzf);
+    const long long t = q / rd.nzf;
+    const int i = (int)(t % rd.nx), j = (int)(t / rd.nx);
+    if (rd.open && k > rd.nz) continue;
+    if (!interior(rd, 0, k)) continue;
+    const double d = rd.rho_b[q] - rd.rho_a[q] + rd.dt * div_e(rd, J, k, i, j);
+    res = fmax(res, fabs(d));
+    rmax = fmax(rmax, fabs(rd.rho_a[q]));
+  }
+  res = block_max(res, sh);
+  rmax = block_max(rmax, sh);
+  if (threadIdx.x == 0) {
+    atomic_max_pos(&rd.ctr->cont_res_bits, res);
+    atomic_max_pos(&rd.ctr->cont_rho_bits, rmax);
+  }
+}
+
+__global__ void k_cont_fin(const RunDev* __restrict__ rdp) {
+  Counters* c = rdp->ctr;
+  const double res = __longlong_as_double((long long)c->cont_res_bits);
+  const double rho = __longlong_as_double((long long)c->cont_rho_bits);
+  const double rel = rho > 0 ? res / rho : res;
+  if (rel > c->cont_max) c->cont_max = rel;
+  c->cont_res_bits = 0;
+  c->cont_rho_bits = 0;
+}
+
+template <typename R>
+__global__ void k_jlast(const RunDev* __restrict__ rdp) {
+  const RunDev& rd = *rdp;
+  for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < rd.npts;
+       q += (long long)gridDim.x * blockDim.x)
+    for (int c = 0; c < 3; ++c) rd.jlast[c][q] = (double)fptr<R>(rd.J[c])[q];
+}
+
+// ------------------------------------------------------------------ Gauss
+// mode 0: store G0 = div E - rho - rho_ion and max|rho_e| (interior);
+// mode 1: max |G - G0| over interior nodes into amax[1]
+template <typename R>
+__global__ __launch_bounds__(256) void k_gauss(const RunDev* __restrict__ rdp, int mode) {
+  __shared__ double sh[4];
+  const RunDev& rd = *rdp;
+  R* const* E = reinterpret_cast<R* const*>(rd.E[rd.ctr->fbuf]);
+  double m = 0.0;
+  for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < rd.npts;
+       q += (long long)gridDim.x * blockDim.x) {
+    const int k = (int)(q % rd.nzf);
+    const long long t = q / rd.nzf;
+    const int i = (int)(t % rd.nx), j = (int)(t / rd.nx);
+    if (rd.open && k > rd.nz) continue;
+    const double G = div_e(rd, E, k, i, j) - rd.rho_a[q] - rd.rho_ion;
+    if (mode == 0) {
+      rd.gauss0[q] = G;
+      if (interior(rd, 0, k)) m = fmax(m, fabs(rd.rho_a[q]));
+    } else if (interior(rd, 0, k)) {
+      m = fmax(m, fabs(G - rd.gauss0[q]));
+    }
+  }
+  m = block_max(m, sh);
+  if (threadIdx.x == 0) {
+    if (mode == 0)
+      atomic_max_pos(reinterpret_cast<unsigned long long*>(&rd.ctr->rho0_max), m);
+    else
+      atomic_max_pos(&rd.ctr->amax[1], m);
+  }
+}
+
+// ------------------------------------------------------------------ energies
+template <typename R>
+__global__ __launch_bounds__(256) void k_diag_fields(const RunDev* __restrict__ rdp) {
+  __shared__ double sh[4];
+  const RunDev& rd = *rdp;
+  const int fb = rd.ctr->fbuf;
+  R* const* E = reinterpret_cast<R* const*>(rd.E[fb]);
+  double ue = 0.0, ub = 0.0, ezm = 0.0;
+  for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < rd.npts;
+       q += (long long)gridDim.x * blockDim.x) {
+    const int k = (int)(q % rd.nzf);
+    const long long t = q / rd.nzf;
+    const int i = (int)(t % rd.nx), j = (int)(t / rd.nx);
+    for (int c = 0; c < 3; ++c) {
+      if (rd.open && k >= zcount(rd, c)) continue;
+      if (!interior(rd, c, k)) continue;
+      const double e = (double)E[c][q];
+      ue += e * e;
+      if (c == 2) ezm = fmax(ezm, fabs(e));
+    }
+    for (int c = 0; c < 3; ++c) {
+      if (rd.open && k >= zcount(rd, 3 + c)) continue;
+      if (!interior(rd, 3 + c, k)) continue;
+      const double b = (double)fptr<R>(rd.B[fb][c])[q] - 0.5 * rd.dt * curl_e(rd, E, c, k, i, j);
+      ub += b * b;
+    }
+  }
+  ue = block_sum(ue, sh);
+  ub = block_sum(ub, sh);
+  ezm = block_max(ezm, sh);
+  if (threadIdx.x == 0) {
+    const double dv = rd.dz * rd.dx * (rd.dims == 3 ? rd.dy : 1.0);
+    atomicAdd(&rd.ctr->acc[0], 0.5 * ue * dv);
+    atomicAdd(&rd.ctr->acc[1], 0.5 * ub * dv);
+    atomic_max_pos(&rd.ctr->amax[0], ezm);
+  }
+}
+
+template <int DIM, typename R>
+__global__ __launch_bounds__(256) void k_diag_particles(const RunDev* __restrict__ rdp) {
+  __shared__ double sh[4];
+  const RunDev& rd = *rdp;
+  const Counters& c = *rd.ctr;
+  const int pb = c.pbuf;
+  double ke = 0.0, cnt = 0.0;
+  for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < c.n_slots;
+       q += (long long)gridDim.x * blockDim.x) {
+    const int cc = rd.cell[pb][q];
+    if (cc < 0) continue;
+    const int k = cell_k(cc);
+    const double z = k + (double)fptr<R>(rd.off[pb][0])[q];
+    const bool inbox = !rd.open || (z >= 0.0 && z < rd.nz);
+    const bool inner = !rd.open || (z >= 2.0 && z < rd.nz - 2);
+    if (inbox) cnt += 1.0;
+    if (inner) {
+      const double ux = (double)fptr<R>(rd.u[pb][0])[q], uy = (double)fptr<R>(rd.u[pb][1])[q];
+      const double uz = (double)fptr<R>(rd.u[pb][2])[q];
+      ke += rd.weight * (sqrt(1.0 + ux * ux + uy * uy + uz * uz) - 1.0);
+    }
+  }
+  ke = block_sum(ke, sh);
+  cnt = block_sum(cnt, sh);
+  if (threadIdx.x == 0) {
+    atomicAdd(&rd.ctr->acc[2], ke);
+    atomicAdd(&rd.ctr->acc[3], cnt);
+  }
+}
+
+// ------------------------------------------------------------------ launches
+static unsigned gridfor(long long n, int B, unsigned cap = 65536) {
+  long long g = (n + B - 1) / B;
+  if (g < 1) g = 1;
+  return (unsigned)(g > cap ? cap : g);
+}
+
+void launch_cont_pre(int dims, int prec, const RunDev* rd, long long npts, long long cap, hipStream_t s) {
+  (void)dims;
+  (void)prec;
+  hipLaunchKernelGGL(k_snap, dim3(gridfor(cap, 256)), dim3(256), 0, s, rd);
+}
+
+// the rho arrays are passed by the host (their device addresses)
+void launch_rho(int dims, int prec, const RunDev* rd, double* rho, long long npts, long long cap,
+                int use_snap, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill, dim3(gridfor(npts, 256)), dim3(256), 0, s, rho, npts, 0.0);
+  const unsigned g = gridfor(cap, 256);
+  if (dims == 3) {
+    if (prec) hipLaunchKernelGGL((k_rho<3, double>), dim3(g), dim3(256), 0, s, rd, rho, use_snap);
+    else hipLaunchKernelGGL((k_rho<3, float>), dim3(g), dim3(256), 0, s, rd, rho, use_snap);
+  } else {
+    if (prec) hipLaunchKernelGGL((k_rho<2, double>), dim3(g), dim3(256), 0, s, rd, rho, use_snap);
+    else hipLaunchKernelGGL((k_rho<2, float>), dim3(g), dim3(256), 0, s, rd, rho, use_snap);
+  }
+}
+
+void launch_cont_post(int dims, int prec, const RunDev* rd, long long npts, long long cap, hipStream_t s) {
+  (void)dims;
+  (void)cap;
+  const unsigned g = gridfor(npts, 256, 4096);
+  if (prec) {
+    hipLaunchKernelGGL(k_cont<double>, dim3(g), dim3(256), 0, s, rd);
+    hipLaunchKernelGGL(k_jlast<double>, dim3(gridfor(npts, 256)), dim3(256), 0, s, rd);
+  } else {
+    hipLaunchKernelGGL(k_cont<float>, dim3(g), dim3(256), 0, s, rd);
+    hipLaunchKernelGGL(k_jlast<float>, dim3(gridfor(npts, 256)), dim3(256), 0, s, rd);
+  }
+  hipLaunchKernelGGL(k_cont_fin, dim3(1), dim3(1), 0, s, rd);
+}
+
+void launch_gauss(int prec, const RunDev* rd, long long npts, int mode, hipStream_t s) {
+  const unsigned g = gridfor(npts, 256, 4096);
+  if (prec) hipLaunchKernelGGL(k_gauss<double>, dim3(g), dim3(256), 0, s, rd, mode);
+  else hipLaunchKernelGGL(k_gauss<float>, dim3(g), dim3(256), 0, s, rd, mode);
+}
+
+void launch_diag(int dims, int prec, const RunDev* rd, long long npts, long long cap, unsigned what,
+                 hipStream_t s) {
+  if (what & 1u) {
+    const unsigned g = gridfor(npts, 256, 4096);
+    if (prec) hipLaunchKernelGGL(k_diag_fields<double>, dim3(g), dim3(256), 0, s, rd);
+    else hipLaunchKernelGGL(k_diag_fields<float>, dim3(g), dim3(256), 0, s, rd);
+  }
+  if (what & 2u) {
+    const unsigned g = gridfor(cap, 256, 4096);
+    if (dims == 3) {
+      if (prec) hipLaunchKernelGGL((k_diag_particles<3, double>), dim3(g), dim3(256), 0, s, rd);
+      else hipLaunchKernelGGL((k_diag_particles<3, float>), dim3(g), dim3(256), 0, s, rd);
+    } else {
+      if (prec) hipLaunchKernelGGL((k_diag_particles<2, double>), dim3(g), dim3(256), 0, s, rd);
+      else hipLaunchKernelGGL((k_diag_particles<2, float>), dim3(g), dim3(256), 0, s, rd);
+    }
+  }
+}
+
+void launch_bshift(int prec, const RunDev* rd, long long npts, int src, int dst, double coef,
+                   hipStream_t s) {
+  const unsigned g = gridfor(npts, 256, 1u << 30);
+  if (prec) hipLaunchKernelGGL(k_bshift<double>, dim3(g), dim3(256), 0, s, rd, src, dst, coef);
+  else hipLaunchKernelGGL(k_bshift<float>, dim3(g), dim3(256), 0, s, rd, src, dst, coef);
+}
+
+}  // namespace pic

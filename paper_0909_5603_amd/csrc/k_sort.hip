@@ -1,0 +1,287 @@
+// Plasma-column injection and the counting sort of particles by tile.
+//
+// Every sort_every steps: (1) create the lattice columns that have drifted
+// into the reservoir beyond z_max (Philox-drawn positions, laboratory
+// Maxwellian momenta boosted to the frame: Sec. 2, second paragraph - the
+// plasma is denser and drifting in the boosted frame), appending them after
+// the current slots; (2) count live particles per tile; (3) exclusive scan of
+// the counts (one workgroup per run); (4) scatter into the other particle
+// buffer, which also drops removed particles; (5) commit the new counts and
+// flip the buffer.  Per-tile atomics are aggregated over the wavefront with
+// ballots: lanes with equal keys elect a leader that makes one atomic add,
+// and each lane's rank inside its group is a popcount of the lower lanes, so
+// a wavefront's particles keep their relative order in the destination
+// (consecutive particles stay in different cells, which keeps the LDS
+// current atomics of the step kernel free of same-address conflicts).
+#include <hip/hip_runtime.h>
+
+#include "launch.hpp"
+#include "pic_dev.hpp"
+
+namespace pic {
+
+// columns and particles the pending injection of this step creates
+__device__ __forceinline__ void pending(const RunDev& rd, const Counters& c, long long& kend,
+                                        long long& nnew) {
+  if (rd.open) {
+    const double shift = rd.beta_b * ((double)c.step * rd.dt) / rd.dz;
+    kend = (long long)rd.nz + rd.reservoir + (long long)ceil(shift);
+  } else {
+    kend = rd.nz;
+  }
+  long long ncol = kend - c.next_col;
+  if (ncol < 0) ncol = 0;
+  nnew = rd.ppc > 0 ? ncol * rd.nperp * rd.ppc : 0;
+}
+
+template <int DIM>
+__device__ __forceinline__ int tile_of(const RunDev& rd, int c) {
+  using T = Tile<DIM>;
+  const int tz = cell_k(c) >> T::LZ;
+  const int tx = cell_i(c) >> T::LX;
+  const int ty = DIM == 3 ? (cell_j(c) >> T::LY) : 0;
+  return (ty * rd.ntx + tx) * rd.ntz + tz;
+}
+
+// wavefront-aggregated atomic add of 1 per active lane to base[key];
+// returns the lane's slot (old value + rank among equal keys)
+__device__ __forceinline__ int wave_agg_add(int* base, int key, bool active) {
+  const int lane = threadIdx.x & 63;
+  unsigned long long pend = __ballot(active);
+  int slot = 0;
+  while (pend) {
+    const int leader = __ffsll((long long)pend) - 1;
+    const int lkey = __shfl(key, leader);
+    const unsigned long long m = __ballot(active && key == lkey);
+    int b = 0;
+    if (lane == leader) b = atomicAdd(base + lkey, __popcll(m));
+    b = __shfl(b, leader);
+    if ((m >> lane) & 1ull) slot = b + __popcll(m & ((1ull << lane) - 1ull));
+    pend &= ~m;
+  }
+  return slot;
+}
+
+// ------------------------------------------------------------------ inject
+template <typename R>
+__global__ __launch_bounds__(256) void k_inject(const BatchTable* __restrict__ bt) {
+  const XcdSplit xs(bt->injblk);
+  for (long long w = xs.beg; w < xs.end; w += xs.stride) {
+    const int r = __builtin_amdgcn_readfirstlane(locate(bt->pre_injblk, bt->n, w));
+    const RunDev& rd = *bt->run[r];
+    const Counters& c = *rd.ctr;
+    if (!sort_due(c, rd.inject_every)) continue;
+    long long kend, nnew;
+    pending(rd, c, kend, nnew);
+    const long long blk = w - bt->pre_injblk[r];
+    if (blk * INJ_CHUNK >= nnew) continue;
+    const int pb = c.pbuf;
+    const long long per_col = rd.nperp * rd.ppc;
+    const double shift = rd.open ? rd.beta_b * ((double)c.step * rd.dt) / rd.dz : 0.0;
+    for (int t = threadIdx.x; t < INJ_CHUNK; t += 256) {
+      const long long q = blk * INJ_CHUNK + t;
+      if (q >= nnew) break;
+      const long long slot = c.n_slots + q;
+      if (slot >= rd.capacity) {
+        atomicOr(&rd.ctr->err, 2u);
+        break;
+      }
+      const long long K = c.next_col + q / per_col;
+      const long long rem = q % per_col;
+      const long long cperp = rem / rd.ppc;
+      const int i = (int)(cperp % rd.nx), j = (int)(cperp / rd.nx);
+      const uint64_t L = (uint64_t)(c.next_col * per_col + q);
+      uint64_t a[4] = {L, 0, 0, 0}, b[4] = {L, 1, 0, 0};
+      philox4x64_10(a, rd.seed, 0);
+      philox4x64_10(b, rd.seed, 0);
+      const double xz = u01(a[0]), xx = u01(a[1]), xy = u01(a[2]);
+      // laboratory Maxwellian (Box-Muller on 1-U in (0,1]), then the boost
+      const double m0 = sqrt(-2.0 * log(1.0 - u01(a[3])));
+      const double p0 = 2.0 * M_PI * u01(b[0]);
+      const double m1 = sqrt(-2.0 * log(1.0 - u01(b[1])));
+      const double p1 = 2.0 * M_PI * u01(b[2]);
+      const double lx = rd.u_th * m0 * cos(p0), ly = rd.u_th * m0 * sin(p0), lz = rd.u_th * m1 * cos(p1);
+      const double gl = sqrt(1.0 + lx * lx + ly * ly + lz * lz);
+      const double bz = rd.gamma_b * (lz - rd.beta_b * gl);
+      // split positions: integer cell + offset stored in R
+      double zeta[3] = {((double)K + xz) - shift, (double)i + xx, (double)j + xy};
+      int cidx[3];
+      R off[3];
+      for (int d = 0; d < 3; ++d) {
+        double fl = floor(zeta[d]);
+        R o = R(zeta[d] - fl);
+        if (o >= R(1)) {
+          o = R(0);
+          fl += 1.0;
+        }
+        cidx[d] = (int)fl;
+        off[d] = o;
+      }
+      if (cidx[1] >= rd.nx) cidx[1] -= rd.nx;
+      if (rd.dims == 3 && cidx[2] >= rd.ny) cidx[2] -= rd.ny;
+      const int cj = rd.dims == 3 ? cidx[2] : 0;
+      rd.cell[pb][slot] = cell_pack(cidx[0], cidx[1], cj);
+      fptr<R>(rd.off[pb][0])[slot] = off[0];
+      fptr<R>(rd.off[pb][1])[slot] = off[1];
+      if (rd.dims == 3) fptr<R>(rd.off[pb][2])[slot] = off[2];
+      fptr<R>(rd.u[pb][0])[slot] = R(lx);
+      fptr<R>(rd.u[pb][1])[slot] = R(ly);
+      fptr<R>(rd.u[pb][2])[slot] = R(bz);
+      rd.pid[pb][slot] = (unsigned)L;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ count
+template <int DIM>
+__global__ __launch_bounds__(256) void k_count(const BatchTable* __restrict__ bt) {
+  const XcdSplit xs(bt->partblk);
+  for (long long w = xs.beg; w < xs.end; w += xs.stride) {
+    const int r = __builtin_amdgcn_readfirstlane(locate(bt->pre_partblk, bt->n, w));
+    const RunDev& rd = *bt->run[r];
+    const Counters& c = *rd.ctr;
+    if (!sort_due(c, rd.inject_every)) continue;
+    long long kend, nnew;
+    pending(rd, c, kend, nnew);
+    long long total = c.n_slots + nnew;
+    if (total > rd.capacity) total = rd.capacity;
+    const long long blk = w - bt->pre_partblk[r];
+    if (blk * PART_CHUNK >= total) continue;
+    const int* cellp = rd.cell[c.pbuf];
+    for (int t = threadIdx.x; t < PART_CHUNK; t += 256) {
+      const long long q = blk * PART_CHUNK + t;
+      int cc = -1;
+      if (q < total) cc = cellp[q];
+      const bool act = cc >= 0;
+      const int key = act ? tile_of<DIM>(rd, cc) : 0;
+      wave_agg_add(rd.tile_count, key, act);
+    }
+  }
+}
+
+// ------------------------------------------------------------------ scan
+__global__ __launch_bounds__(1024) void k_scan(const BatchTable* __restrict__ bt) {
+  if ((int)blockIdx.x >= bt->n) return;
+  const RunDev& rd = *bt->run[blockIdx.x];
+  Counters* c = rd.ctr;
+  if (!sort_due(*c, rd.inject_every)) return;
+  __shared__ int wsum[16];
+  __shared__ int carry_s;
+  const int n = rd.ntiles;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int per = (n + 1023) / 1024;
+  const int beg = threadIdx.x * per;
+  int sum = 0;
+  for (int q = 0; q < per; ++q) {
+    const int t = beg + q;
+    if (t < n) sum += rd.tile_count[t];
+  }
+  // inclusive scan of the per-thread sums: wavefront shuffles, then waves
+  int v = sum;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int o = __shfl_up(v, d);
+    if (lane >= d) v += o;
+  }
+  if (lane == 63) wsum[wave] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int acc = 0;
+    for (int q = 0; q < 16; ++q) {
+      const int x = wsum[q];
+      wsum[q] = acc;
+      acc += x;
+    }
+    carry_s = acc;
+  }
+  __syncthreads();
+  int run = wsum[wave] + v - sum;  // exclusive prefix of this thread's segment
+  for (int q = 0; q < per; ++q) {
+    const int t = beg + q;
+    if (t < n) {
+      const int cnt = rd.tile_count[t];
+      rd.tile_start[t] = run;
+      rd.tile_cursor[t] = run;
+      rd.tile_count[t] = 0;
+      run += cnt;
+    }
+  }
+  if (threadIdx.x == 0) {
+    rd.tile_start[n] = carry_s;
+    c->n_live = carry_s;
+  }
+}
+
+// ------------------------------------------------------------------ scatter
+template <int DIM, typename R>
+__global__ __launch_bounds__(256) void k_scatter(const BatchTable* __restrict__ bt) {
+  const XcdSplit xs(bt->partblk);
+  for (long long w = xs.beg; w < xs.end; w += xs.stride) {
+    const int r = __builtin_amdgcn_readfirstlane(locate(bt->pre_partblk, bt->n, w));
+    const RunDev& rd = *bt->run[r];
+    const Counters& c = *rd.ctr;
+    if (!sort_due(c, rd.inject_every)) continue;
+    long long kend, nnew;
+    pending(rd, c, kend, nnew);
+    long long total = c.n_slots + nnew;
+    if (total > rd.capacity) total = rd.capacity;
+    const long long blk = w - bt->pre_partblk[r];
+    if (blk * PART_CHUNK >= total) continue;
+    const int src = c.pbuf, dst = src ^ 1;
+    const int* cellp = rd.cell[src];
+    for (int t = threadIdx.x; t < PART_CHUNK; t += 256) {
+      const long long q = blk * PART_CHUNK + t;
+      int cc = -1;
+      if (q < total) cc = cellp[q];
+      const bool act = cc >= 0;
+      const int key = act ? tile_of<DIM>(rd, cc) : 0;
+      const int slot = wave_agg_add(rd.tile_cursor, key, act);
+      if (act) {
+        rd.cell[dst][slot] = cc;
+        fptr<R>(rd.off[dst][0])[slot] = fptr<R>(rd.off[src][0])[q];
+        fptr<R>(rd.off[dst][1])[slot] = fptr<R>(rd.off[src][1])[q];
+        if (DIM == 3) fptr<R>(rd.off[dst][2])[slot] = fptr<R>(rd.off[src][2])[q];
+        fptr<R>(rd.u[dst][0])[slot] = fptr<R>(rd.u[src][0])[q];
+        fptr<R>(rd.u[dst][1])[slot] = fptr<R>(rd.u[src][1])[q];
+        fptr<R>(rd.u[dst][2])[slot] = fptr<R>(rd.u[src][2])[q];
+        rd.pid[dst][slot] = rd.pid[src][q];
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------ commit
+__global__ void k_commit(const BatchTable* __restrict__ bt) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= bt->n) return;
+  const RunDev& rd = *bt->run[r];
+  Counters* c = rd.ctr;
+  if (!sort_due(*c, rd.inject_every)) return;
+  long long kend, nnew;
+  pending(rd, *c, kend, nnew);
+  if (c->n_slots + nnew > rd.capacity) c->err |= 2u;
+  if (kend > c->next_col) c->next_col = kend;
+  c->n_slots = c->n_live;
+  c->pbuf ^= 1;
+  c->fresh = 1;
+  c->last_sort = c->step;
+}
+
+template <int DIM, typename R>
+static void chain(const BatchTable* bt, int nruns, int grid, hipStream_t s) {
+  hipLaunchKernelGGL((k_inject<R>), dim3(grid), dim3(256), 0, s, bt);
+  hipLaunchKernelGGL((k_count<DIM>), dim3(grid), dim3(256), 0, s, bt);
+  hipLaunchKernelGGL(k_scan, dim3(nruns), dim3(1024), 0, s, bt);
+  hipLaunchKernelGGL((k_scatter<DIM, R>), dim3(grid), dim3(256), 0, s, bt);
+  hipLaunchKernelGGL(k_commit, dim3((nruns + 63) / 64), dim3(64), 0, s, bt);
+}
+
+void launch_sort_chain(int dims, int prec, const BatchTable* bt, int nruns, int grid, hipStream_t s) {
+  if (dims == 3) {
+    if (prec) chain<3, double>(bt, nruns, grid, s); else chain<3, float>(bt, nruns, grid, s);
+  } else {
+    if (prec) chain<2, double>(bt, nruns, grid, s); else chain<2, float>(bt, nruns, grid, s);
+  }
+}
+
+}  // namespace pic

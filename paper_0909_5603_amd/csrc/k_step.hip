@@ -1,0 +1,717 @@
+// One boosted-frame PIC step on gfx950: the fused particle kernel (gather,
+// push, move, charge-conserving deposit) and the single-pass Yee update.
+//
+// Particle kernel.  Particles are stored tile by tile (counting sort every
+// sort_every steps).  A workgroup takes one tile: it stages E^n and
+// B^{n-1/2} of the tile's window in LDS, advances B to integer time there,
+// zeroes an LDS current window, runs its particles through
+//   gather (linear interpolation at each component's Yee stagger),
+//   push (modified Lorentz force with analytic gamma, Vay 2008),
+//   move (int cell + in-cell offset, one carry per dimension),
+//   deposit (Esirkepov 2001, linear shape, into LDS with ds_add),
+// and flushes the window's current to HBM with global atomics.  The window
+// follows the bounding box of the tile's particles measured in the previous
+// step, so it tracks the plasma as it streams through the boosted frame.
+// Particles whose stencil leaves the window take a slow path that reads and
+// deposits in HBM directly: results never depend on the window.
+//
+// Field kernel.  State is (E^n, B^{n-1/2}) in ping-pong buffers.  One thread
+// per grid point computes B^{n+1/2} = B^{n-1/2} - dt curl E^n for the four
+// B points its E update needs, then E^{n+1} = E^n + dt (curl B^{n+1/2} - J -
+// J_ion), first-order Mur on the tangential E at open z ends, and clears J.
+// This is the standard leapfrog, algebraically equal to two half steps of B
+// around the E step with E and B both at integer time.
+#include <hip/hip_runtime.h>
+
+#include "launch.hpp"
+#include "pic_dev.hpp"
+#include "pusher.hpp"
+
+namespace pic {
+
+// ------------------------------------------------------------------ helpers
+template <typename R>
+struct W1 {
+  R n0, n1;  // node-centred weights at offsets 0, +1
+  R h0, h1;  // half-cell weights at offsets hb, hb+1
+  int hb;
+};
+
+template <typename R>
+__device__ __forceinline__ W1<R> weights(R o) {
+  W1<R> w;
+  w.n0 = R(1) - o;
+  w.n1 = o;
+  const bool up = o >= R(0.5);
+  w.hb = up ? 0 : -1;
+  w.h0 = up ? R(1.5) - o : R(0.5) - o;
+  w.h1 = up ? o - R(0.5) : R(0.5) + o;
+  return w;
+}
+
+// linear interpolation of component C from its own stagger
+template <int DIM, int C, typename R, class F>
+__device__ __forceinline__ R interp(const W1<R>* w, F&& fetch) {
+  constexpr bool sz = stag(C, 0), sx = stag(C, 1), sy = stag(C, 2);
+  const R z0 = sz ? w[0].h0 : w[0].n0, z1 = sz ? w[0].h1 : w[0].n1;
+  const R x0 = sx ? w[1].h0 : w[1].n0, x1 = sx ? w[1].h1 : w[1].n1;
+  const int oz = sz ? w[0].hb : 0, ox = sx ? w[1].hb : 0;
+  if constexpr (DIM == 3) {
+    const R y0 = sy ? w[2].h0 : w[2].n0, y1 = sy ? w[2].h1 : w[2].n1;
+    const int oy = sy ? w[2].hb : 0;
+    const R a = z0 * fetch(C, oz, ox, oy) + z1 * fetch(C, oz + 1, ox, oy);
+    const R b = z0 * fetch(C, oz, ox + 1, oy) + z1 * fetch(C, oz + 1, ox + 1, oy);
+    const R c = z0 * fetch(C, oz, ox, oy + 1) + z1 * fetch(C, oz + 1, ox, oy + 1);
+    const R d = z0 * fetch(C, oz, ox + 1, oy + 1) + z1 * fetch(C, oz + 1, ox + 1, oy + 1);
+    return y0 * (x0 * a + x1 * b) + y1 * (x0 * c + x1 * d);
+  } else {
+    const R a = z0 * fetch(C, oz, ox, 0) + z1 * fetch(C, oz + 1, ox, 0);
+    const R b = z0 * fetch(C, oz, ox + 1, 0) + z1 * fetch(C, oz + 1, ox + 1, 0);
+    return x0 * a + x1 * b;
+  }
+}
+
+// Esirkepov shape data along one dimension.  The 3-node window starts at
+// min(old cell, new cell) = old cell + base.  S0 = old node shapes, DS = new
+// minus old, P[a] = sum_{a'<=a} DS[a'] (P[2] = 0), written directly from the
+// offsets so that no cancellation is lost.
+template <typename R>
+struct Dep1 {
+  R S0[3], DS[3], P[2];
+  int base;
+};
+
+template <typename R>
+__device__ __forceinline__ Dep1<R> dep1(R o0, R o1, int carry) {
+  Dep1<R> d;
+  const bool dn = carry < 0, up = carry > 0;
+  const R a0 = R(1) - o0, a1 = R(1) - o1;
+  d.S0[0] = dn ? R(0) : a0;
+  d.S0[1] = dn ? a0 : o0;
+  d.S0[2] = dn ? o0 : R(0);
+  const R s10 = up ? R(0) : a1;
+  const R s11 = up ? a1 : o1;
+  const R s12 = up ? o1 : R(0);
+  d.DS[0] = s10 - d.S0[0];
+  d.DS[1] = s11 - d.S0[1];
+  d.DS[2] = s12 - d.S0[2];
+  d.P[0] = up ? (o0 - R(1)) : dn ? a1 : (o0 - o1);
+  d.P[1] = up ? -o1 : dn ? o0 : R(0);
+  d.base = dn ? -1 : 0;
+  return d;
+}
+
+// offset carry after a move of less than one cell (CFL)
+template <typename R>
+__device__ __forceinline__ int carry(R& o) {
+  if (o < R(0)) {
+    o += R(1);
+    if (o >= R(1)) {  // the sum rounded up to 1: stay in the cell at offset 0
+      o = R(0);
+      return 0;
+    }
+    return -1;
+  }
+  if (o >= R(1)) {
+    o -= R(1);
+    return 1;
+  }
+  return 0;
+}
+
+// charge-conserving current of one particle, linear shape (Esirkepov 2001).
+// add(comp, dk, di, dj, v) receives offsets from the particle's old cell.
+template <int DIM, typename R, class A>
+__device__ __forceinline__ void deposit(const Dep1<R>* d, R cz, R cx, R cy, R cyv, A&& add) {
+  const Dep1<R>& Z = d[0];
+  const Dep1<R>& X = d[1];
+  if constexpr (DIM == 3) {
+    const Dep1<R>& Y = d[2];
+    R Ay[3], By[3], Ax[3], Bx[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      Ay[c] = Y.S0[c] + R(0.5) * Y.DS[c];
+      By[c] = R(0.5) * Y.S0[c] + R(1.0 / 3.0) * Y.DS[c];
+      Ax[c] = X.S0[c] + R(0.5) * X.DS[c];
+      Bx[c] = R(0.5) * X.S0[c] + R(1.0 / 3.0) * X.DS[c];
+    }
+    // J_z(face a; node b, c) = cz P_z[a] (S0x Ay + DSx By)
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const R f = X.S0[b] * Ay[c] + X.DS[b] * By[c];
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+          const R v = cz * Z.P[a] * f;
+          if (v != R(0)) add(2, Z.base + a, X.base + b, Y.base + c, v);
+        }
+      }
+    // J_x(node a; face b; node c) = cx P_x[b] (S0z Ay + DSz By)
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const R f = Z.S0[a] * Ay[c] + Z.DS[a] * By[c];
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          const R v = cx * X.P[b] * f;
+          if (v != R(0)) add(0, Z.base + a, X.base + b, Y.base + c, v);
+        }
+      }
+    // J_y(node a, b; face c) = cy P_y[c] (S0z Ax + DSz Bx)
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        const R f = Z.S0[a] * Ax[b] + Z.DS[a] * Bx[b];
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          const R v = cy * Y.P[c] * f;
+          if (v != R(0)) add(1, Z.base + a, X.base + b, Y.base + c, v);
+        }
+      }
+  } else {
+    R Ax[3], Bx[3];
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      Ax[b] = X.S0[b] + R(0.5) * X.DS[b];
+      Bx[b] = R(0.5) * X.S0[b] + R(1.0 / 3.0) * X.DS[b];
+    }
+    // J_z(face a; node b) = cz P_z[a] (S0x + DSx/2)
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        const R v = cz * Z.P[a] * Ax[b];
+        if (v != R(0)) add(2, Z.base + a, X.base + b, 0, v);
+      }
+    // J_x(node a; face b) = cx P_x[b] (S0z + DSz/2)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const R az = Z.S0[a] + R(0.5) * Z.DS[a];
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        const R v = cx * X.P[b] * az;
+        if (v != R(0)) add(0, Z.base + a, X.base + b, 0, v);
+      }
+    }
+    // J_y(node a, b) = cyv * time-averaged shape
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        const R v = cyv * (Z.S0[a] * Ax[b] + Z.DS[a] * Bx[b]);
+        if (v != R(0)) add(1, Z.base + a, X.base + b, 0, v);
+      }
+  }
+}
+
+// E value with HBM index handling (zero outside an open z range)
+template <int DIM, typename R>
+__device__ __forceinline__ R gE(const RunDev& rd, R* const* E, int comp, int k, int i, int j) {
+  i = wrapi(i, rd.nx);
+  j = DIM == 3 ? wrapi(j, rd.ny) : 0;
+  if (rd.open) {
+    if (k < 0 || k >= zcount(rd, comp)) return R(0);
+  } else {
+    k = wrapi(k, rd.nz);
+  }
+  return E[comp][gidx(rd, k, i, j)];
+}
+
+// field value at integer time n for the slow path: E directly, B advanced
+// from n-1/2 on the fly
+template <int DIM, typename R>
+__device__ R fetch_hbm(const RunDev& rd, R* const* E, R* const* B, int comp, int k, int i, int j) {
+  if (comp < 3) return gE<DIM, R>(rd, E, comp, k, i, j);
+  int ii = wrapi(i, rd.nx), jj = DIM == 3 ? wrapi(j, rd.ny) : 0, kk = k;
+  if (rd.open) {
+    if (k < 0 || k >= zcount(rd, comp)) return R(0);
+  } else {
+    kk = wrapi(k, rd.nz);
+  }
+  const R b = B[comp - 3][gidx(rd, kk, ii, jj)];
+  const R idz = R(1.0 / rd.dz), idx = R(1.0 / rd.dx), idy = DIM == 3 ? R(1.0 / rd.dy) : R(0);
+  R curl;
+  if (comp == 3)
+    curl = (DIM == 3 ? (gE<DIM, R>(rd, E, 2, k, i, j + 1) - gE<DIM, R>(rd, E, 2, k, i, j)) * idy : R(0)) -
+           (gE<DIM, R>(rd, E, 1, k + 1, i, j) - gE<DIM, R>(rd, E, 1, k, i, j)) * idz;
+  else if (comp == 4)
+    curl = (gE<DIM, R>(rd, E, 0, k + 1, i, j) - gE<DIM, R>(rd, E, 0, k, i, j)) * idz -
+           (gE<DIM, R>(rd, E, 2, k, i + 1, j) - gE<DIM, R>(rd, E, 2, k, i, j)) * idx;
+  else
+    curl = (gE<DIM, R>(rd, E, 1, k, i + 1, j) - gE<DIM, R>(rd, E, 1, k, i, j)) * idx -
+           (DIM == 3 ? (gE<DIM, R>(rd, E, 0, k, i, j + 1) - gE<DIM, R>(rd, E, 0, k, i, j)) * idy : R(0));
+  return b - R(0.5 * rd.dt) * curl;
+}
+
+template <int DIM, typename R>
+__device__ __forceinline__ void add_hbm(const RunDev& rd, int comp, int k, int i, int j, R v) {
+  i = wrapi(i, rd.nx);
+  j = DIM == 3 ? wrapi(j, rd.ny) : 0;
+  if (rd.open) {
+    if (k < 0 || k >= zcount(rd, comp)) return;  // current outside the box is dropped
+  } else {
+    k = wrapi(k, rd.nz);
+  }
+  atomicAdd(fptr<R>(rd.J[comp]) + gidx(rd, k, i, j), v);
+}
+
+// ------------------------------------------------------------------ particles
+template <int DIM, typename R, int BLOCK, int PUSHER>
+__global__ __launch_bounds__(BLOCK) void k_particles(const BatchTable* __restrict__ bt) {
+  using T = Tile<DIM>;
+  constexpr int WZM = T::WZ, WXM = T::WX, WYM = T::WY;
+  constexpr int WV = WZM * WXM * WYM;
+  constexpr int SY = (DIM == 3) ? WZM * WXM : 0;  // LDS stride of y
+  __shared__ R sF[9][WV];  // Ex Ey Ez Bx By Bz Jx Jy Jz of the tile window
+  __shared__ int sred[6][BLOCK / 64];
+
+  const XcdSplit xs(bt->tiles);
+  for (long long w = xs.beg; w < xs.end; w += xs.stride) {
+    const int r = __builtin_amdgcn_readfirstlane(locate(bt->pre_tiles, bt->n, w));
+    const RunDev& rd = *bt->run[r];
+    const int tile = (int)(w - bt->pre_tiles[r]);
+    const Counters& ctr = *rd.ctr;
+    const int pb = ctr.pbuf, fb = ctr.fbuf, bb = ctr.bbuf, fresh = ctr.fresh;
+    const int nx = rd.nx, ny = rd.ny, nz = rd.nz, nzf = rd.nzf;
+    const bool open = rd.open != 0;
+
+    const int ntz = rd.ntz, ntx = rd.ntx;
+    const int tz = tile % ntz, rest = tile / ntz;
+    const int tx = rest % ntx, ty = rest / ntx;
+    const int t0[3] = {tz * T::TZ, tx * T::TX, ty * T::TY};
+    const long long p0 = rd.tile_start[tile], p1 = rd.tile_start[tile + 1];
+    int* bbw = rd.bbox[bb ^ 1] + 6 * tile;
+    if (p0 >= p1) {
+      if (threadIdx.x == 0) {
+        bbw[0] = bbw[1] = bbw[2] = 1 << 20;
+        bbw[3] = bbw[4] = bbw[5] = -(1 << 20);
+      }
+      continue;
+    }
+    int lo[3] = {0, 0, 0}, hi[3] = {T::TZ - 1, T::TX - 1, T::TY - 1};
+    if (!fresh) {
+      const int* bbr = rd.bbox[bb] + 6 * tile;
+      if (bbr[0] <= bbr[3]) {
+        for (int d = 0; d < 3; ++d) {
+          lo[d] = bbr[d];
+          hi[d] = bbr[3 + d];
+        }
+      }
+    }
+    int Wd[3], w0[3];
+    Wd[0] = min(hi[0] - lo[0] + 4, WZM);
+    Wd[1] = min(hi[1] - lo[1] + 4, WXM);
+    Wd[2] = DIM == 3 ? min(hi[2] - lo[2] + 4, WYM) : 1;
+    for (int d = 0; d < 3; ++d) w0[d] = t0[d] + lo[d] - 1;
+    if (DIM == 2) w0[2] = 0;
+
+    R* const* Eg = reinterpret_cast<R* const*>(rd.E[fb]);
+    R* const* Bg = reinterpret_cast<R* const*>(rd.B[fb]);
+    const R dt = R(rd.dt);
+
+    // ---- stage E^n and B^{n-1/2} of the window; clear the current window
+    __syncthreads();
+    const int nwin = Wd[0] * Wd[1] * Wd[2];
+    for (int q = threadIdx.x; q < nwin; q += BLOCK) {
+      const int rz = q % Wd[0];
+      const int t = q / Wd[0];
+      const int rx = t % Wd[1], ry = t / Wd[1];
+      const int s = (ry * WXM + rx) * WZM + rz;
+      const int gk = w0[0] + rz;
+      const int gi = wrapi(w0[1] + rx, nx);
+      const int gj = DIM == 3 ? wrapi(w0[2] + ry, ny) : 0;
+      bool zn = true, zh = true;
+      int kk = gk;
+      if (open) {
+        zn = gk >= 0 && gk <= nz;
+        zh = gk >= 0 && gk < nz;
+        kk = min(max(gk, 0), nzf - 1);
+      } else {
+        kk = wrapi(gk, nz);
+      }
+      const long long g = ((long long)gj * nx + gi) * nzf + kk;
+      const R ex = Eg[0][g], ey = Eg[1][g], ez = Eg[2][g];
+      const R bx = Bg[0][g], by = Bg[1][g], bz = Bg[2][g];
+      sF[0][s] = zn ? ex : R(0);
+      sF[1][s] = zn ? ey : R(0);
+      sF[2][s] = zh ? ez : R(0);
+      sF[3][s] = zh ? bx : R(0);
+      sF[4][s] = zh ? by : R(0);
+      sF[5][s] = zn ? bz : R(0);
+      sF[6][s] = R(0);
+      sF[7][s] = R(0);
+      sF[8][s] = R(0);
+    }
+    __syncthreads();
+    // ---- B^n = B^{n-1/2} - dt/2 curl E^n on the window (last layer unused)
+    {
+      const R hdt = R(0.5) * dt;
+      const R idz = R(1.0 / rd.dz), idx = R(1.0 / rd.dx), idy = DIM == 3 ? R(1.0 / rd.dy) : R(0);
+      const int bz_ = Wd[0] - 1, bx_ = Wd[1] - 1, by_ = DIM == 3 ? Wd[2] - 1 : 1;
+      const int nb = bz_ * bx_ * by_;
+      for (int q = threadIdx.x; q < nb; q += BLOCK) {
+        const int rz = q % bz_;
+        const int t = q / bz_;
+        const int rx = t % bx_, ry = t / bx_;
+        const int s = (ry * WXM + rx) * WZM + rz;
+        const int gk = w0[0] + rz;
+        const bool zn = !open || (gk >= 0 && gk <= nz);
+        const bool zh = !open || (gk >= 0 && gk < nz);
+        const R ex = sF[0][s], ey = sF[1][s], ez = sF[2][s];
+        const R ex_z = sF[0][s + 1], ey_z = sF[1][s + 1];
+        const R ez_x = sF[2][s + WZM], ey_x = sF[1][s + WZM];
+        const R ez_y = sF[2][s + SY], ex_y = sF[0][s + SY];
+        if (zh) {
+          sF[3][s] -= hdt * ((ez_y - ez) * idy - (ey_z - ey) * idz);
+          sF[4][s] -= hdt * ((ex_z - ex) * idz - (ez_x - ez) * idx);
+        }
+        if (zn) sF[5][s] -= hdt * ((ey_x - ey) * idx - (ex_y - ex) * idy);
+      }
+    }
+    __syncthreads();
+
+    // ---- particles
+    int* __restrict__ cellp = rd.cell[pb];
+    R* __restrict__ o0p = fptr<R>(rd.off[pb][0]);
+    R* __restrict__ o1p = fptr<R>(rd.off[pb][1]);
+    R* __restrict__ o2p = fptr<R>(rd.off[pb][2]);
+    R* __restrict__ uxp = fptr<R>(rd.u[pb][0]);
+    R* __restrict__ uyp = fptr<R>(rd.u[pb][1]);
+    R* __restrict__ uzp = fptr<R>(rd.u[pb][2]);
+    const R eps = R(-0.5) * dt;
+    const R cdz = R(rd.dt / rd.dz), cdx = R(rd.dt / rd.dx), cdy = R(rd.dt / rd.dy);
+    const double wgt = rd.weight;
+    R cz, cx, cy;
+    if (DIM == 3) {
+      cz = R(wgt / (rd.dx * rd.dy * rd.dt));
+      cx = R(wgt / (rd.dz * rd.dy * rd.dt));
+      cy = R(wgt / (rd.dz * rd.dx * rd.dt));
+    } else {
+      cz = R(wgt / (rd.dx * rd.dt));
+      cx = R(wgt / (rd.dz * rd.dt));
+      cy = R(0);
+    }
+    const R cyv0 = R(-wgt / (rd.dz * rd.dx));
+    const int gz = rd.gz, gx = rd.gx, gy = rd.gy, ztop = rd.ztop;
+    int bmin0 = 1 << 20, bmin1 = 1 << 20, bmin2 = 1 << 20;
+    int bmax0 = -(1 << 20), bmax1 = -(1 << 20), bmax2 = -(1 << 20);
+    bool bad = false;
+
+    for (long long p = p0 + threadIdx.x; p < p1; p += BLOCK) {
+      const int c = cellp[p];
+      if (c < 0) continue;  // removed
+      const int k = cell_k(c), i = cell_i(c), j = DIM == 3 ? cell_j(c) : 0;
+      const int rk = open ? k - t0[0] : relw(k, t0[0], nz, gz);
+      const int ri = relw(i, t0[1], nx, gx);
+      const int rj = DIM == 3 ? relw(j, t0[2], ny, gy) : 0;
+      const int wk = rk - lo[0] + 1, wi = ri - lo[1] + 1, wj = DIM == 3 ? rj - lo[2] + 1 : 0;
+      const bool fast = wk >= 1 && wk <= Wd[0] - 3 && wi >= 1 && wi <= Wd[1] - 3 &&
+                        (DIM == 2 || (wj >= 1 && wj <= Wd[2] - 3));
+      R o[3];
+      o[0] = o0p[p];
+      o[1] = o1p[p];
+      o[2] = DIM == 3 ? o2p[p] : R(0);
+      R ux = uxp[p], uy = uyp[p], uz = uzp[p];
+      W1<R> wt[3];
+      wt[0] = weights(o[0]);
+      wt[1] = weights(o[1]);
+      if (DIM == 3) wt[2] = weights(o[2]);
+      R ex, ey, ez, bx, by, bz;
+      const int base = (wj * WXM + wi) * WZM + wk;
+      if (fast) {
+        auto f = [&](int comp, int dk, int di, int dj) -> R {
+          return sF[comp][base + dk + di * WZM + dj * SY];
+        };
+        ex = interp<DIM, 0, R>(wt, f);
+        ey = interp<DIM, 1, R>(wt, f);
+        ez = interp<DIM, 2, R>(wt, f);
+        bx = interp<DIM, 3, R>(wt, f);
+        by = interp<DIM, 4, R>(wt, f);
+        bz = interp<DIM, 5, R>(wt, f);
+      } else {
+        auto f = [&](int comp, int dk, int di, int dj) -> R {
+          return fetch_hbm<DIM, R>(rd, Eg, Bg, comp, k + dk, i + di, j + dj);
+        };
+        ex = interp<DIM, 0, R>(wt, f);
+        ey = interp<DIM, 1, R>(wt, f);
+        ez = interp<DIM, 2, R>(wt, f);
+        bx = interp<DIM, 3, R>(wt, f);
+        by = interp<DIM, 4, R>(wt, f);
+        bz = interp<DIM, 5, R>(wt, f);
+      }
+      if (PUSHER == 1)
+        push_boris<R>(ux, uy, uz, ex, ey, ez, bx, by, bz, eps);
+      else
+        push_vay<R>(ux, uy, uz, ex, ey, ez, bx, by, bz, eps);
+      const R g1 = sqrt(R(1) + ux * ux + uy * uy + uz * uz);
+      bad |= !(g1 < R(3.0e38));
+      const R ig = R(1) / g1;
+      R on[3];
+      on[0] = o[0] + cdz * uz * ig;
+      on[1] = o[1] + cdx * ux * ig;
+      on[2] = DIM == 3 ? o[2] + cdy * uy * ig : R(0);
+      int cr[3];
+      cr[0] = carry(on[0]);
+      cr[1] = carry(on[1]);
+      cr[2] = DIM == 3 ? carry(on[2]) : 0;
+      Dep1<R> dd[3];
+      dd[0] = dep1(o[0], on[0], cr[0]);
+      dd[1] = dep1(o[1], on[1], cr[1]);
+      if (DIM == 3) dd[2] = dep1(o[2], on[2], cr[2]);
+      const R cyv = cyv0 * uy * ig;
+      if (fast) {
+        deposit<DIM, R>(dd, cz, cx, cy, cyv, [&](int comp, int dk, int di, int dj, R v) {
+          atomicAdd(&sF[6 + comp][base + dk + di * WZM + dj * SY], v);
+        });
+      } else {
+        deposit<DIM, R>(dd, cz, cx, cy, cyv, [&](int comp, int dk, int di, int dj, R v) {
+          add_hbm<DIM, R>(rd, comp, k + dk, i + di, j + dj, v);
+        });
+      }
+      int k1 = k + cr[0];
+      int i1 = i + cr[1];
+      i1 = i1 < 0 ? i1 + nx : (i1 >= nx ? i1 - nx : i1);
+      int j1 = 0;
+      if (DIM == 3) {
+        j1 = j + cr[2];
+        j1 = j1 < 0 ? j1 + ny : (j1 >= ny ? j1 - ny : j1);
+      }
+      bool dead = false;
+      if (open) {
+        dead = k1 < 0 || k1 >= ztop;
+      } else {
+        k1 = k1 < 0 ? k1 + nz : (k1 >= nz ? k1 - nz : k1);
+      }
+      cellp[p] = cell_pack(k1, i1, j1) | (dead ? (int)DEAD : 0);
+      o0p[p] = on[0];
+      o1p[p] = on[1];
+      if (DIM == 3) o2p[p] = on[2];
+      uxp[p] = ux;
+      uyp[p] = uy;
+      uzp[p] = uz;
+      if (!dead) {
+        const int nk = open ? k1 - t0[0] : relw(k1, t0[0], nz, gz);
+        const int ni = relw(i1, t0[1], nx, gx);
+        bmin0 = min(bmin0, nk);
+        bmax0 = max(bmax0, nk);
+        bmin1 = min(bmin1, ni);
+        bmax1 = max(bmax1, ni);
+        if (DIM == 3) {
+          const int nj = relw(j1, t0[2], ny, gy);
+          bmin2 = min(bmin2, nj);
+          bmax2 = max(bmax2, nj);
+        }
+      }
+    }
+    if (bad) atomicOr(&rd.ctr->err, 1u);
+    // ---- bounding box of the new positions
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+      bmin0 = min(bmin0, __shfl_xor(bmin0, m));
+      bmin1 = min(bmin1, __shfl_xor(bmin1, m));
+      bmin2 = min(bmin2, __shfl_xor(bmin2, m));
+      bmax0 = max(bmax0, __shfl_xor(bmax0, m));
+      bmax1 = max(bmax1, __shfl_xor(bmax1, m));
+      bmax2 = max(bmax2, __shfl_xor(bmax2, m));
+    }
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0) {
+      sred[0][wave] = bmin0;
+      sred[1][wave] = bmin1;
+      sred[2][wave] = bmin2;
+      sred[3][wave] = bmax0;
+      sred[4][wave] = bmax1;
+      sred[5][wave] = bmax2;
+    }
+    __syncthreads();
+    if (threadIdx.x < 6) {
+      const int t = threadIdx.x;
+      int v = sred[t][0];
+      for (int q = 1; q < BLOCK / 64; ++q) v = t < 3 ? min(v, sred[t][q]) : max(v, sred[t][q]);
+      if (DIM == 2 && (t == 2 || t == 5)) v = 0;
+      bbw[t] = v;
+    }
+    // ---- flush the current window to HBM
+    for (int q = threadIdx.x; q < nwin; q += BLOCK) {
+      const int rz = q % Wd[0];
+      const int t = q / Wd[0];
+      const int rx = t % Wd[1], ry = t / Wd[1];
+      const int s = (ry * WXM + rx) * WZM + rz;
+      const R jx = sF[6][s], jy = sF[7][s], jz = sF[8][s];
+      if (jx == R(0) && jy == R(0) && jz == R(0)) continue;
+      int gk = w0[0] + rz;
+      const int gi = wrapi(w0[1] + rx, nx);
+      const int gj = DIM == 3 ? wrapi(w0[2] + ry, ny) : 0;
+      bool zn = true, zh = true;
+      if (open) {
+        zn = gk >= 0 && gk <= nz;
+        zh = gk >= 0 && gk < nz;
+      } else {
+        gk = wrapi(gk, nz);
+      }
+      const long long g = ((long long)gj * nx + gi) * nzf + gk;
+      if (zn && jx != R(0)) atomicAdd(fptr<R>(rd.J[0]) + g, jx);
+      if (zn && jy != R(0)) atomicAdd(fptr<R>(rd.J[1]) + g, jy);
+      if (zh && jz != R(0)) atomicAdd(fptr<R>(rd.J[2]) + g, jz);
+    }
+  }
+}
+
+// ------------------------------------------------------------------ fields
+template <int DIM, typename R>
+__global__ __launch_bounds__(256) void k_fields(const BatchTable* __restrict__ bt) {
+  const XcdSplit xs(bt->cellblk);
+  for (long long w = xs.beg; w < xs.end; w += xs.stride) {
+    const int r = __builtin_amdgcn_readfirstlane(locate(bt->pre_cellblk, bt->n, w));
+    const RunDev& rd = *bt->run[r];
+    const long long q = (w - bt->pre_cellblk[r]) * CELL_BLOCK + threadIdx.x;
+    if (q >= rd.npts) continue;
+    const int nzf = rd.nzf, nx = rd.nx, ny = rd.ny, nz = rd.nz;
+    const int k = (int)(q % nzf);
+    const long long t = q / nzf;
+    const int i = (int)(t % nx), j = (int)(t / nx);
+    const int fb = rd.ctr->fbuf;
+    const bool open = rd.open != 0;
+    R* const* E = reinterpret_cast<R* const*>(rd.E[fb]);
+    R* const* Bm = reinterpret_cast<R* const*>(rd.B[fb]);
+    R* const* En = reinterpret_cast<R* const*>(rd.E[fb ^ 1]);
+    R* const* Bn = reinterpret_cast<R* const*>(rd.B[fb ^ 1]);
+    R* const* J = reinterpret_cast<R* const*>(rd.J);
+    const R dt = R(rd.dt);
+    const R idz = R(1.0 / rd.dz), idx = R(1.0 / rd.dx), idy = DIM == 3 ? R(1.0 / rd.dy) : R(0);
+
+    auto wx = [&](int ii) { return ii < 0 ? ii + nx : (ii >= nx ? ii - nx : ii); };
+    auto wy = [&](int jj) { return DIM == 3 ? (jj < 0 ? jj + ny : (jj >= ny ? jj - ny : jj)) : 0; };
+    // z index of component c, or -1 if outside the open range
+    auto zk = [&](int c, int kk) {
+      if (open) return (kk >= 0 && kk < (stag(c, 0) ? nz : nz + 1)) ? kk : -1;
+      return kk < 0 ? kk + nz : (kk >= nz ? kk - nz : kk);
+    };
+    auto Ev = [&](int c, int kk, int ii, int jj) -> R {
+      const int z = zk(c, kk);
+      if (z < 0) return R(0);
+      return E[c][((long long)wy(jj) * nx + wx(ii)) * nzf + z];
+    };
+    // B^{n+1/2} = B^{n-1/2} - dt curl E^n at (kk, ii, jj)
+    auto Bh = [&](int c, int kk, int ii, int jj) -> R {
+      const int z = zk(3 + c, kk);
+      if (z < 0) return R(0);
+      R curl;
+      if (c == 0)
+        curl = (DIM == 3 ? (Ev(2, kk, ii, jj + 1) - Ev(2, kk, ii, jj)) * idy : R(0)) -
+               (Ev(1, kk + 1, ii, jj) - Ev(1, kk, ii, jj)) * idz;
+      else if (c == 1)
+        curl = (Ev(0, kk + 1, ii, jj) - Ev(0, kk, ii, jj)) * idz -
+               (Ev(2, kk, ii + 1, jj) - Ev(2, kk, ii, jj)) * idx;
+      else
+        curl = (Ev(1, kk, ii + 1, jj) - Ev(1, kk, ii, jj)) * idx -
+               (DIM == 3 ? (Ev(0, kk, ii, jj + 1) - Ev(0, kk, ii, jj)) * idy : R(0));
+      return Bm[c][((long long)wy(jj) * nx + wx(ii)) * nzf + z] - dt * curl;
+    };
+    const R jion = R(rd.jion_z);
+    const long long g0 = ((long long)j * nx + i) * nzf;
+    auto Jv = [&](int c, int kk) -> R {
+      const int z = zk(c, kk);
+      return z < 0 ? R(0) : J[c][g0 + z];
+    };
+    // E^{n+1} at (kk, i, j) from Ampere's law
+    auto Enew = [&](int c, int kk) -> R {
+      if (c == 0)
+        return Ev(0, kk, i, j) +
+               dt * ((DIM == 3 ? (Bh(2, kk, i, j) - Bh(2, kk, i, j - 1)) * idy : R(0)) -
+                     (Bh(1, kk, i, j) - Bh(1, kk - 1, i, j)) * idz - Jv(0, kk));
+      if (c == 1)
+        return Ev(1, kk, i, j) + dt * ((Bh(0, kk, i, j) - Bh(0, kk - 1, i, j)) * idz -
+                                       (Bh(2, kk, i, j) - Bh(2, kk, i - 1, j)) * idx - Jv(1, kk));
+      return Ev(2, kk, i, j) +
+             dt * ((Bh(1, kk, i, j) - Bh(1, kk, i - 1, j)) * idx -
+                   (DIM == 3 ? (Bh(0, kk, i, j) - Bh(0, kk, i, j - 1)) * idy : R(0)) - Jv(2, kk) - jion);
+    };
+    const long long g = g0 + k;
+    const R cm = R((rd.dt - rd.dz) / (rd.dt + rd.dz));
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {  // tangential E (node-centred in z)
+      R v;
+      if (open && k == 0)
+        v = Ev(c, 1, i, j) + cm * (Enew(c, 1) - Ev(c, 0, i, j));
+      else if (open && k == nz)
+        v = Ev(c, nz - 1, i, j) + cm * (Enew(c, nz - 1) - Ev(c, nz, i, j));
+      else
+        v = Enew(c, k);
+      En[c][g] = v;
+    }
+    En[2][g] = (zk(2, k) >= 0) ? Enew(2, k) : R(0);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) Bn[c][g] = Bh(c, k, i, j);
+    J[0][g] = R(0);
+    J[1][g] = R(0);
+    J[2][g] = R(0);
+  }
+}
+
+__global__ void k_advance(const BatchTable* __restrict__ bt) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= bt->n) return;
+  Counters* c = bt->run[r]->ctr;
+  c->step += 1;
+  c->fbuf ^= 1;
+  c->bbuf ^= 1;
+  c->fresh = 0;
+}
+
+// ------------------------------------------------------------------ launch
+template <int DIM, typename R>
+struct PBlock {
+  static constexpr int value = 256;
+};
+
+int grid_particles(int dims, int prec, int ncu) {
+  size_t lds;
+  if (dims == 3)
+    lds = 9 * sizeof(float) * (prec ? 2 : 1) * Tile<3>::WZ * Tile<3>::WX * Tile<3>::WY;
+  else
+    lds = 9 * sizeof(float) * (prec ? 2 : 1) * Tile<2>::WZ * Tile<2>::WX;
+  int per_cu = (int)((160 * 1024) / (lds + 1024));
+  if (per_cu < 1) per_cu = 1;
+  if (per_cu > 8) per_cu = 8;
+  int g = ncu * per_cu;
+  return (g + 7) & ~7;
+}
+
+int grid_generic(int ncu) { return ncu * 8; }
+
+template <int DIM, typename R>
+static void lp(int pusher, const BatchTable* bt, int grid, hipStream_t s) {
+  constexpr int B = PBlock<DIM, R>::value;
+  if (pusher == 1)
+    hipLaunchKernelGGL((k_particles<DIM, R, B, 1>), dim3(grid), dim3(B), 0, s, bt);
+  else
+    hipLaunchKernelGGL((k_particles<DIM, R, B, 0>), dim3(grid), dim3(B), 0, s, bt);
+}
+
+void launch_particles(int dims, int prec, int pusher, const BatchTable* bt, int grid, hipStream_t s) {
+  if (dims == 3) {
+    if (prec) lp<3, double>(pusher, bt, grid, s); else lp<3, float>(pusher, bt, grid, s);
+  } else {
+    if (prec) lp<2, double>(pusher, bt, grid, s); else lp<2, float>(pusher, bt, grid, s);
+  }
+}
+
+void launch_fields(int dims, int prec, const BatchTable* bt, int grid, hipStream_t s) {
+  if (dims == 3) {
+    if (prec) hipLaunchKernelGGL((k_fields<3, double>), dim3(grid), dim3(256), 0, s, bt);
+    else hipLaunchKernelGGL((k_fields<3, float>), dim3(grid), dim3(256), 0, s, bt);
+  } else {
+    if (prec) hipLaunchKernelGGL((k_fields<2, double>), dim3(grid), dim3(256), 0, s, bt);
+    else hipLaunchKernelGGL((k_fields<2, float>), dim3(grid), dim3(256), 0, s, bt);
+  }
+}
+
+void launch_advance(const BatchTable* bt, int nruns, hipStream_t s) {
+  hipLaunchKernelGGL(k_advance, dim3((nruns + 63) / 64), dim3(64), 0, s, bt);
+}
+
+}  // namespace pic

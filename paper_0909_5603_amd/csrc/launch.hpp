@@ -1,0 +1,39 @@
+// Host-side launch entry points of the kernel translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "pic_dev.hpp"
+
+namespace pic {
+
+// persistent grid sizes (workgroups), multiples of 8 (one share per XCD)
+int grid_particles(int dims, int prec, int ncu);
+int grid_generic(int ncu);
+
+// one step, split in launches (all read their run set from the batch table)
+void launch_sort_chain(int dims, int prec, const BatchTable* bt, int nruns, int grid, hipStream_t s);
+void launch_particles(int dims, int prec, int pusher, const BatchTable* bt, int grid, hipStream_t s);
+void launch_fields(int dims, int prec, const BatchTable* bt, int grid, hipStream_t s);
+void launch_advance(const BatchTable* bt, int nruns, hipStream_t s);
+
+// initialisation (one run)
+void launch_init_fields(int dims, int prec, const RunDev* rd, long long npts, hipStream_t s);
+
+// diagnostics (one run)
+void launch_cont_pre(int dims, int prec, const RunDev* rd, long long npts, long long cap, hipStream_t s);
+void launch_rho(int dims, int prec, const RunDev* rd, double* rho, long long npts, long long cap,
+                int use_snap, hipStream_t s);
+void launch_cont_post(int dims, int prec, const RunDev* rd, long long npts, long long cap, hipStream_t s);
+void launch_gauss(int prec, const RunDev* rd, long long npts, int mode, hipStream_t s);
+void launch_diag(int dims, int prec, const RunDev* rd, long long npts, long long cap, unsigned what,
+                 hipStream_t s);
+// B[dst] = B[src] + coef curl E[fbuf]; src/dst < 0 select fbuf / fbuf^1
+void launch_bshift(int prec, const RunDev* rd, long long npts, int src, int dst, double coef,
+                   hipStream_t s);
+
+// pusher microbenchmark
+void launch_push_bench(int prec, int pusher, long long n, double dt, const double B[3], void* Ex,
+                       void* u, int* cell, void* off, hipStream_t s);
+
+}  // namespace pic

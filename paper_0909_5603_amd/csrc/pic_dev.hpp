@@ -1,0 +1,204 @@
+// Device-side run descriptor, batch table and small device helpers for the
+// gfx950 boosted-frame PIC kernels.  Everything that changes during a run
+// (step index, ping-pong buffer parities, particle counts, error word) lives
+// in device memory, so every kernel sequence can be captured once in a HIP
+// graph and replayed, and several runs can share one launch through a batch
+// table of descriptors.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pic {
+
+// ---------------------------------------------------------------- constants
+constexpr int MAX_BATCH = 256;
+
+// Packed particle cell: k + KOFF in bits 0..10, i in bits 11..20, j in bits
+// 21..30, bit 31 = removed.  KOFF lets a particle that just left through
+// z = 0 keep its position for the continuity diagnostic.
+constexpr int KOFF = 4;
+constexpr int KBITS = 11, IBITS = 10, JBITS = 10;
+constexpr int KMASK = (1 << KBITS) - 1, IMASK = (1 << IBITS) - 1, JMASK = (1 << JBITS) - 1;
+constexpr unsigned DEAD = 0x80000000u;
+
+// Tile geometry (cells) and the largest LDS window a tile may use.  The
+// window spans the tile's particle bounding box widened by one cell below
+// and two above (gather and deposit stencils): W = extent + 3, plus one cell
+// of slack for the fractional drift of the plasma between two sorts in z.
+template <int DIM> struct Tile;
+template <> struct Tile<3> {
+  static constexpr int LZ = 3, LX = 3, LY = 2;
+  static constexpr int TZ = 1 << LZ, TX = 1 << LX, TY = 1 << LY;
+  static constexpr int WZ = TZ + 6, WX = TX + 5, WY = TY + 5;
+};
+template <> struct Tile<2> {
+  static constexpr int LZ = 4, LX = 4, LY = 0;
+  static constexpr int TZ = 1 << LZ, TX = 1 << LX, TY = 1;
+  static constexpr int WZ = TZ + 6, WX = TX + 5, WY = 1;
+};
+
+// Yee staggering per component (half-cell flags in z, x, y):
+// Ex(0,1,0) Ey(0,0,1) Ez(1,0,0) Bx(1,0,1) By(1,1,0) Bz(0,1,1); J like E.
+__host__ __device__ constexpr int stag(int comp, int d) {
+  return (comp == 0) ? (d == 1) : (comp == 1) ? (d == 2) : (comp == 2) ? (d == 0)
+       : (comp == 3) ? (d != 1) : (comp == 4) ? (d != 2) : (d != 0);
+}
+
+// ---------------------------------------------------------------- state
+struct Counters {
+  long long step;      // index n of the next step
+  long long n_slots;   // particle slots in the current buffer (live + removed + tail)
+  long long n_live;    // live particles after the last sort
+  long long next_col;  // next plasma lattice column to create
+  long long last_sort; // step of the last sort (-1: none)
+  long long n_new;     // particles created by the pending injection
+  long long k_end;     // column bound of the pending injection
+  int pbuf, fbuf, bbuf, fresh;
+  unsigned err;
+  int pad0;
+  // continuity diagnostic (max over steps, as bit patterns of non-negative doubles)
+  unsigned long long cont_res_bits, cont_rho_bits;
+  double cont_max;
+  double rho0_max;
+  // diagnostic accumulators
+  double acc[4];
+  unsigned long long amax[4];
+  unsigned long long cnt[2];
+};
+
+struct RunDev {
+  int dims, nz, nx, ny, nzf, open, ppc, reservoir, ztop, inject_every;
+  int ntz, ntx, nty, ntiles;
+  int gx, gy, gz;       // wrap guards for tile-relative coordinates
+  int pusher, diag_flags, pol_axis;
+  long long capacity, nperp, npts, max_new;
+  double dt, dz, dx, dy;
+  double beta_b, gamma_b, dminus, dplus, weight, jion_z, rho_ion, u_th;
+  double k0_lab, E0_lab, L_lab, zc_boost, waist;
+  unsigned long long seed;
+  // arrays (device addresses inside the caller's buffer); element type is
+  // float (split-precision path) or double (FP64 path)
+  void* E[2][3];
+  void* B[2][3];  // B at half-integer time: B^{n-1/2} in B[fbuf]
+  void* J[3];
+  int* cell[2];
+  void* off[2][3];
+  void* u[2][3];
+  unsigned* pid[2];
+  int* tile_start;  // ntiles + 1
+  int* tile_count;  // ntiles
+  int* tile_cursor; // ntiles
+  int* bbox[2];     // 6 ints per tile: lo z,x,y then hi z,x,y (tile-relative)
+  double* rho_a;
+  double* rho_b;
+  double* gauss0;
+  double* jlast[3];
+  int* cell_snap;
+  Counters* ctr;
+};
+
+// A set of runs advanced by the same launches.  Work items of every kernel
+// are enumerated run by run; pre_* are exclusive prefix sums of the per-run
+// item counts.
+struct BatchTable {
+  int n;
+  int pad;
+  long long tiles, cellblk, partblk, injblk;
+  const RunDev* run[MAX_BATCH];
+  long long pre_tiles[MAX_BATCH + 1];
+  long long pre_cellblk[MAX_BATCH + 1];
+  long long pre_partblk[MAX_BATCH + 1];
+  long long pre_injblk[MAX_BATCH + 1];
+};
+
+constexpr int CELL_BLOCK = 256;     // cells per field work item
+constexpr int PART_CHUNK = 4096;    // particle slots per sort work item
+constexpr int INJ_CHUNK = 4096;     // created particles per injection work item
+
+// ---------------------------------------------------------------- helpers
+__device__ __forceinline__ int locate(const long long* pre, int n, long long w) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (pre[mid] <= w) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Persistent work distribution: workgroup b runs on XCD b % 8 (round-robin
+// dispatch), so each XCD takes one contiguous eighth of the items and the
+// tiles that share halo data meet in the same L2.
+struct XcdSplit {
+  long long beg, end, stride;
+  __device__ XcdSplit(long long total) {
+    const int G = gridDim.x;
+    const int x = blockIdx.x & 7;
+    const int per = G >> 3;
+    const long long chunk = (total + 7) >> 3;
+    beg = x * chunk + (blockIdx.x >> 3);
+    end = (x + 1) * chunk < total ? (x + 1) * chunk : total;
+    stride = per;
+  }
+};
+
+__device__ __forceinline__ int wrapi(int i, int n) {
+  int r = i % n;
+  return r < 0 ? r + n : r;
+}
+// tile-relative coordinate of a periodic index, in [-g, n-g)
+__device__ __forceinline__ int relw(int i, int t0, int n, int g) {
+  int r = i - t0 + g;
+  r %= n;
+  if (r < 0) r += n;
+  return r - g;
+}
+
+__device__ __forceinline__ int cell_k(int c) { return (c & KMASK) - KOFF; }
+__device__ __forceinline__ int cell_i(int c) { return (c >> KBITS) & IMASK; }
+__device__ __forceinline__ int cell_j(int c) { return (c >> (KBITS + IBITS)) & JMASK; }
+__device__ __forceinline__ int cell_pack(int k, int i, int j) {
+  return (k + KOFF) | (i << KBITS) | (j << (KBITS + IBITS));
+}
+
+// number of valid z indices of a component (open z: nodes 0..nz, half
+// points 0..nz-1; periodic: nz)
+__device__ __forceinline__ int zcount(const RunDev& r, int comp) {
+  return r.open ? (stag(comp, 0) ? r.nz : r.nz + 1) : r.nz;
+}
+
+__device__ __forceinline__ long long gidx(const RunDev& r, int k, int i, int j) {
+  return ((long long)j * r.nx + i) * r.nzf + k;
+}
+
+// Philox4x64-10 (Salmon et al., SC'11)
+__device__ __forceinline__ void philox4x64_10(uint64_t c[4], uint64_t k0, uint64_t k1) {
+  const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+  const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    uint64_t hi0 = __umul64hi(M0, c[0]), lo0 = M0 * c[0];
+    uint64_t hi1 = __umul64hi(M1, c[2]), lo1 = M1 * c[2];
+    uint64_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+    c[0] = n0; c[1] = lo1; c[2] = n2; c[3] = lo0;
+    k0 += W0; k1 += W1;
+  }
+}
+__device__ __forceinline__ double u01(uint64_t r) {
+  return (double)(r >> 11) * (1.0 / 9007199254740992.0);
+}
+
+// bit pattern max for non-negative doubles
+__device__ __forceinline__ void atomic_max_pos(unsigned long long* a, double v) {
+  atomicMax(a, (unsigned long long)__double_as_longlong(v));
+}
+
+// the sort/injection of a step runs when the step is a multiple of the
+// cadence and has not been sorted yet
+__device__ __forceinline__ bool sort_due(const Counters& c, int every) {
+  return (c.step % every) == 0 && c.step != c.last_sort;
+}
+
+template <typename R> __device__ __forceinline__ R* fptr(void* p) { return reinterpret_cast<R*>(p); }
+
+}  // namespace pic

@@ -1,0 +1,65 @@
+// Relativistic pushers (u = gamma v), device side.
+//
+// push_vay: the modified Lorentz-force form of the paper (Sec. 2, first
+// paragraph; Vay, Phys. Plasmas 15, 056701 (2008)): the magnetic force uses
+// the average of the old and new velocity, so for E + v x B = 0 the electric
+// and magnetic kicks cancel exactly; the resulting implicit equation for the
+// new gamma is solved in closed form.  The vector algebra runs in R (float
+// or double); the gamma solve always runs in double, because at large gamma
+// the "1 +" and the tau^2 terms of sigma vanish below FP32 resolution.
+//
+// push_boris: the Boris pusher the paper replaces (kept as a control).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace pic {
+
+template <typename R>
+__device__ __forceinline__ void push_vay(R& ux, R& uy, R& uz, R ex, R ey, R ez, R bx, R by, R bz,
+                                         R eps) {
+  const R g = sqrt(R(1) + ux * ux + uy * uy + uz * uz);
+  const R ig = R(1) / g;
+  const R vx = ux * ig, vy = uy * ig, vz = uz * ig;
+  // half electric kick plus magnetic force with the old velocity, then the
+  // second electric half kick: u' = u + eps (2E + v x B)
+  const R upx = ux + eps * (R(2) * ex + (vy * bz - vz * by));
+  const R upy = uy + eps * (R(2) * ey + (vz * bx - vx * bz));
+  const R upz = uz + eps * (R(2) * ez + (vx * by - vy * bx));
+  const R tx = eps * bx, ty = eps * by, tz = eps * bz;
+  // gamma_new^2 = (sigma + sqrt(sigma^2 + 4 (tau^2 + u*^2))) / 2,
+  // sigma = 1 + u'^2 - tau^2, u* = u'.tau   (FP64)
+  const double dux = upx, duy = upy, duz = upz, dtx = tx, dty = ty, dtz = tz;
+  const double ustar = dux * dtx + duy * dty + duz * dtz;
+  const double tau2 = dtx * dtx + dty * dty + dtz * dtz;
+  const double sigma = 1.0 + (dux * dux + duy * duy + duz * duz) - tau2;
+  const double a4 = 4.0 * (tau2 + ustar * ustar);
+  const double disc = sqrt(sigma * sigma + a4);
+  const double g2 = sigma >= 0.0 ? 0.5 * (sigma + disc) : 0.5 * a4 / (disc - sigma);
+  const R ign = R(1.0 / sqrt(g2));
+  // u_new = s (u' + (u'.t) t + u' x t),  t = tau / gamma_new,  s = 1/(1+t^2)
+  const R ttx = tx * ign, tty = ty * ign, ttz = tz * ign;
+  const R s = R(1) / (R(1) + ttx * ttx + tty * tty + ttz * ttz);
+  const R upt = upx * ttx + upy * tty + upz * ttz;
+  ux = s * (upx + upt * ttx + (upy * ttz - upz * tty));
+  uy = s * (upy + upt * tty + (upz * ttx - upx * ttz));
+  uz = s * (upz + upt * ttz + (upx * tty - upy * ttx));
+}
+
+template <typename R>
+__device__ __forceinline__ void push_boris(R& ux, R& uy, R& uz, R ex, R ey, R ez, R bx, R by,
+                                           R bz, R eps) {
+  const R mx = ux + eps * ex, my = uy + eps * ey, mz = uz + eps * ez;
+  const R ig = R(1) / sqrt(R(1) + mx * mx + my * my + mz * mz);
+  const R tx = eps * bx * ig, ty = eps * by * ig, tz = eps * bz * ig;
+  const R px = mx + (my * tz - mz * ty);
+  const R py = my + (mz * tx - mx * tz);
+  const R pz = mz + (mx * ty - my * tx);
+  const R f = R(2) / (R(1) + tx * tx + ty * ty + tz * tz);
+  const R sx = f * tx, sy = f * ty, sz = f * tz;
+  ux = mx + (py * sz - pz * sy) + eps * ex;
+  uy = my + (pz * sx - px * sz) + eps * ey;
+  uz = mz + (px * sy - py * sx) + eps * ez;
+}
+
+}  // namespace pic

@@ -1,0 +1,72 @@
+"""The C-ABI library loads, exports every function include/pic.h declares,
+and its pure host calls (sizing, validation) work without a GPU."""
+import os
+import re
+
+import pytest
+
+from paper_0909_5603_amd import workloads
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def pic():
+    from paper_0909_5603_amd import pic as m
+
+    if not os.path.exists(m.LIB_PATH):
+        from paper_0909_5603_amd import build
+
+        build.build()
+    m.lib()
+    return m
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "pic.h")).read()
+    return sorted(set(re.findall(r"^(?:pic_status|const char\*)\s+(pic_\w+)\(", src, re.M)))
+
+
+def test_exports_every_declared_symbol(pic):
+    names = _declared()
+    assert len(names) >= 12
+    L = pic.lib()
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(pic.EXPORTS) == names
+
+
+def test_state_bytes_scale_with_the_workload(pic):
+    small = pic.pic_state_bytes(pic.make_params(workloads.config("c1")))
+    big = pic.pic_state_bytes(pic.make_params(workloads.config("c5")))
+    fp64 = pic.pic_state_bytes(pic.make_params(workloads.config("c5"), "fp64"))
+    assert 1e6 < small < 1e8
+    # 537M particles x 2 buffers x 32 B plus fields
+    assert 3.0e10 < big < 6.0e10
+    assert fp64 > 1.5 * big
+
+
+@pytest.mark.parametrize("over,status", [
+    (dict(nx=20), -1), (dict(dims=4), -1), (dict(cfl=1.0), -4), (dict(cfl=0.0), -4),
+    (dict(gamma_boost=0.5), -1), (dict(ppc=-1), -1), (dict(sort_every=0), -1),
+    (dict(nz=4000), -1), (dict(pol_axis=3), -1),
+])
+def test_invalid_parameters(pic, over, status):
+    cfg = workloads.config("c1", **over)
+    with pytest.raises(pic.PicError) as e:
+        pic.pic_state_bytes(pic.make_params(cfg))
+    assert e.value.status == status
+    assert pic.pic_last_error()
+
+
+def test_null_arguments(pic):
+    import ctypes
+
+    L = pic.lib()
+    assert L.pic_free(None) == 0
+    assert L.pic_state_bytes(None, None) == -1
+    assert L.pic_step(None, 1) == -1
+    assert L.pic_diag(None, 0, None) == -1
+    out = ctypes.c_void_p()
+    p = pic.make_params(workloads.config("c1"))
+    assert L.pic_init_boosted(ctypes.byref(p), None, 0, None, ctypes.byref(out)) == -1
