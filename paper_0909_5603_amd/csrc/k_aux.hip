@@ -232,7 +232,7 @@ template <typename R>
 __global__ __launch_bounds__(256) void k_cont(const RunDev* __restrict__ rdp) {
   __shared__ double sh[4];
   const RunDev& rd = *rdp;
-  R* const* J = reinterpret_cast<R* const*>(rd.J);
+  R* const* J = reinterpret_cast<R* const*>(rd.J[rd.ctr->fbuf]);
   double res = 0.0, rmax = 0.0;
   for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < rd.npts;
        q += (long long)gridDim.x * blockDim.x) {
@@ -268,7 +268,7 @@ __global__ void k_jlast(const RunDev* __restrict__ rdp) {
   const RunDev& rd = *rdp;
   for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < rd.npts;
        q += (long long)gridDim.x * blockDim.x)
-    for (int c = 0; c < 3; ++c) rd.jlast[c][q] = (double)fptr<R>(rd.J[c])[q];
+    for (int c = 0; c < 3; ++c) rd.jlast[c][q] = (double)fptr<R>(rd.J[rd.ctr->fbuf][c])[q];
 }
 
 // ------------------------------------------------------------------ Gauss

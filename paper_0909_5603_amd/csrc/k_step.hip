@@ -18,9 +18,12 @@
 // Field kernel.  State is (E^n, B^{n-1/2}) in ping-pong buffers.  One thread
 // per grid point computes B^{n+1/2} = B^{n-1/2} - dt curl E^n for the four
 // B points its E update needs, then E^{n+1} = E^n + dt (curl B^{n+1/2} - J -
-// J_ion), first-order Mur on the tangential E at open z ends, and clears J.
-// This is the standard leapfrog, algebraically equal to two half steps of B
-// around the E step with E and B both at integer time.
+// J_ion), and first-order Mur on the tangential E at open z ends.  The current
+// is double-buffered: the step deposits into J[fbuf], the field kernel reads
+// it (the Mur thread also reads its interior neighbour's) and clears the other
+// buffer, into which the next step deposits.  This is the standard leapfrog,
+// algebraically equal to two half steps of B around the E step with E and B
+// both at integer time.
 #include <hip/hip_runtime.h>
 
 #include "launch.hpp"
@@ -247,7 +250,7 @@ __device__ R fetch_hbm(const RunDev& rd, R* const* E, R* const* B, int comp, int
 }
 
 template <int DIM, typename R>
-__device__ __forceinline__ void add_hbm(const RunDev& rd, int comp, int k, int i, int j, R v) {
+__device__ __forceinline__ void add_hbm(const RunDev& rd, int fb, int comp, int k, int i, int j, R v) {
   i = wrapi(i, rd.nx);
   j = DIM == 3 ? wrapi(j, rd.ny) : 0;
   if (rd.open) {
@@ -255,7 +258,7 @@ __device__ __forceinline__ void add_hbm(const RunDev& rd, int comp, int k, int i
   } else {
     k = wrapi(k, rd.nz);
   }
-  atomicAdd(fptr<R>(rd.J[comp]) + gidx(rd, k, i, j), v);
+  atomicAdd(fptr<R>(rd.J[fb][comp]) + gidx(rd, k, i, j), v);
 }
 
 // ------------------------------------------------------------------ particles
@@ -468,7 +471,7 @@ __global__ __launch_bounds__(BLOCK) void k_particles(const BatchTable* __restric
         });
       } else {
         deposit<DIM, R>(dd, cz, cx, cy, cyv, [&](int comp, int dk, int di, int dj, R v) {
-          add_hbm<DIM, R>(rd, comp, k + dk, i + di, j + dj, v);
+          add_hbm<DIM, R>(rd, fb, comp, k + dk, i + di, j + dj, v);
         });
       }
       int k1 = k + cr[0];
@@ -553,9 +556,9 @@ __global__ __launch_bounds__(BLOCK) void k_particles(const BatchTable* __restric
         gk = wrapi(gk, nz);
       }
       const long long g = ((long long)gj * nx + gi) * nzf + gk;
-      if (zn && jx != R(0)) atomicAdd(fptr<R>(rd.J[0]) + g, jx);
-      if (zn && jy != R(0)) atomicAdd(fptr<R>(rd.J[1]) + g, jy);
-      if (zh && jz != R(0)) atomicAdd(fptr<R>(rd.J[2]) + g, jz);
+      if (zn && jx != R(0)) atomicAdd(fptr<R>(rd.J[fb][0]) + g, jx);
+      if (zn && jy != R(0)) atomicAdd(fptr<R>(rd.J[fb][1]) + g, jy);
+      if (zh && jz != R(0)) atomicAdd(fptr<R>(rd.J[fb][2]) + g, jz);
     }
   }
 }
@@ -579,7 +582,8 @@ __global__ __launch_bounds__(256) void k_fields(const BatchTable* __restrict__ b
     R* const* Bm = reinterpret_cast<R* const*>(rd.B[fb]);
     R* const* En = reinterpret_cast<R* const*>(rd.E[fb ^ 1]);
     R* const* Bn = reinterpret_cast<R* const*>(rd.B[fb ^ 1]);
-    R* const* J = reinterpret_cast<R* const*>(rd.J);
+    R* const* J = reinterpret_cast<R* const*>(rd.J[fb]);
+    R* const* Jnext = reinterpret_cast<R* const*>(rd.J[fb ^ 1]);
     const R dt = R(rd.dt);
     const R idz = R(1.0 / rd.dz), idx = R(1.0 / rd.dx), idy = DIM == 3 ? R(1.0 / rd.dy) : R(0);
 
@@ -646,9 +650,11 @@ __global__ __launch_bounds__(256) void k_fields(const BatchTable* __restrict__ b
     En[2][g] = (zk(2, k) >= 0) ? Enew(2, k) : R(0);
 #pragma unroll
     for (int c = 0; c < 3; ++c) Bn[c][g] = Bh(c, k, i, j);
-    J[0][g] = R(0);
-    J[1][g] = R(0);
-    J[2][g] = R(0);
+    // the current read above (own point and, at the Mur ends, the next
+    // interior point) stays intact; the buffer of the next step is cleared
+    Jnext[0][g] = R(0);
+    Jnext[1][g] = R(0);
+    Jnext[2][g] = R(0);
   }
 }
 

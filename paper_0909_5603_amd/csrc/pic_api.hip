@@ -52,7 +52,7 @@ struct Derived {
 
 struct Layout {
   size_t rundev, ctr, tab1, tabB;
-  size_t E[2][3], B[2][3], J[3];
+  size_t E[2][3], B[2][3], J[2][3];
   size_t cell[2], off[2][3], u[2][3], pid[2];
   size_t tile_start, tile_count, tile_cursor, bbox[2];
   size_t rho_a, rho_b, gauss0, jlast[3], cell_snap;
@@ -147,7 +147,8 @@ void layout(const pic_lab_params* p, const Derived& d, Layout& L) {
     for (int c = 0; c < 3; ++c) L.E[b][c] = take(fb);
   for (int b = 0; b < 2; ++b)
     for (int c = 0; c < 3; ++c) L.B[b][c] = take(fb);
-  for (int c = 0; c < 3; ++c) L.J[c] = take(fb);
+  for (int b = 0; b < 2; ++b)
+    for (int c = 0; c < 3; ++c) L.J[b][c] = take(fb);
   L.tile_start = take(sizeof(int) * (d.ntiles + 1));
   L.tile_count = take(sizeof(int) * d.ntiles);
   L.tile_cursor = take(sizeof(int) * d.ntiles);
@@ -412,7 +413,8 @@ pic_status pic_init_boosted(const pic_lab_params* p, void* dev_buf, size_t bytes
       h.u[b][c] = at<void>(r, L.u[b][c]);
     }
   for (int c = 0; c < 3; ++c) {
-    h.J[c] = at<void>(r, L.J[c]);
+    h.J[0][c] = at<void>(r, L.J[0][c]);
+    h.J[1][c] = at<void>(r, L.J[1][c]);
     h.jlast[c] = at<double>(r, L.jlast[c]);
   }
   for (int b = 0; b < 2; ++b) {

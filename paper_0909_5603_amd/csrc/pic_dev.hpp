@@ -81,7 +81,8 @@ struct RunDev {
   // float (split-precision path) or double (FP64 path)
   void* E[2][3];
   void* B[2][3];  // B at half-integer time: B^{n-1/2} in B[fbuf]
-  void* J[3];
+  void* J[2][3];  // the step deposits into J[fbuf]; the field kernel reads it
+                  // and clears J[fbuf^1] for the next step
   int* cell[2];
   void* off[2][3];
   void* u[2][3];

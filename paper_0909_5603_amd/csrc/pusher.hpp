@@ -37,13 +37,17 @@ __device__ __forceinline__ void push_vay(R& ux, R& uy, R& uz, R ex, R ey, R ez, 
   const double disc = sqrt(sigma * sigma + a4);
   const double g2 = sigma >= 0.0 ? 0.5 * (sigma + disc) : 0.5 * a4 / (disc - sigma);
   const R ign = R(1.0 / sqrt(g2));
-  // u_new = s (u' + (u'.t) t + u' x t),  t = tau / gamma_new,  s = 1/(1+t^2)
+  // u_new = s (u' + (u'.t) t + u' x t),  t = tau / gamma_new,  s = 1/(1+t^2),
+  // evaluated as u' + s ((u'.t) t + u' x t - t^2 u'): the small rotation is
+  // formed on its own and added once, so the large components of u' are
+  // rounded once per step instead of being scaled by s
   const R ttx = tx * ign, tty = ty * ign, ttz = tz * ign;
-  const R s = R(1) / (R(1) + ttx * ttx + tty * tty + ttz * ttz);
+  const R t2 = ttx * ttx + tty * tty + ttz * ttz;
+  const R s = R(1) / (R(1) + t2);
   const R upt = upx * ttx + upy * tty + upz * ttz;
-  ux = s * (upx + upt * ttx + (upy * ttz - upz * tty));
-  uy = s * (upy + upt * tty + (upz * ttx - upx * ttz));
-  uz = s * (upz + upt * ttz + (upx * tty - upy * ttx));
+  ux = upx + s * (upt * ttx + (upy * ttz - upz * tty) - t2 * upx);
+  uy = upy + s * (upt * tty + (upz * ttx - upx * ttz) - t2 * upy);
+  uz = upz + s * (upt * ttz + (upx * tty - upy * ttx) - t2 * upz);
 }
 
 template <typename R>

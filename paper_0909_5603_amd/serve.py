@@ -49,7 +49,8 @@ class Done:
 
 
 class GpuExecutor:
-    """Runs requests with libpic on one GPU and one shared stream."""
+    """Runs requests with libpic on one GPU.  All runs live on one stream:
+    pic_step_batch enqueues their batched steps there."""
 
     def __init__(self, precision: str = "fp32", keep_results: bool = False):
         import torch
@@ -57,13 +58,9 @@ class GpuExecutor:
         from . import pic
 
         self.pic = pic
-        self.torch = torch
         self.precision = precision
         self.keep = keep_results
         self.stream = torch.cuda.Stream()
-        # a second stream for initialisation, so new runs are set up while
-        # the batch keeps computing
-        self.init_stream = torch.cuda.Stream()
         self.t0 = time.perf_counter()
 
     def now(self) -> float:
@@ -73,33 +70,18 @@ class GpuExecutor:
         return self.pic.pic_state_bytes(self.pic.make_params(req.cfg, self.precision))
 
     def admit(self, req: Request):
-        run = self.pic.Run(req.cfg, self.precision, stream=self.init_stream)
-        # later steps go to the shared stream (the initialisation has
-        # completed: pic_init_boosted synchronises its stream)
-        run.stream = self.stream
-        self.pic.lib()  # already loaded
-        self._rebind(run)
-        return run
-
-    def _rebind(self, run):
-        # the library keeps the stream given at init; runs that join the batch
-        # are stepped on the first run's stream by pic_step_batch, so the
-        # handle's own stream only matters for diagnostics, which synchronise
-        run._batch_stream = self.stream
+        # initialisation (laser transform, plasma creation, first sort) runs
+        # on the shared stream and has completed when this returns
+        return self.pic.Run(req.cfg, self.precision, stream=self.stream)
 
     def advance(self, runs, nsteps):
         self.pic.pic_step_batch([r.handle for r in runs], nsteps)
 
     def wait(self):
         self.stream.synchronize()
-        self.init_stream.synchronize()
 
     def release(self, run):
-        res = None
-        if self.keep:
-            self.init_stream.synchronize()
-            self.stream.synchronize()
-            res = run.diag(self.pic.PIC_DIAG_FIELDS | self.pic.PIC_DIAG_PARTICLES)
+        res = run.diag(self.pic.PIC_DIAG_FIELDS | self.pic.PIC_DIAG_PARTICLES) if self.keep else None
         run.close()
         return res
 

@@ -42,13 +42,16 @@ def _u_relerr(g, o):
 
 
 def _field_relerr(run, st):
-    worst = 0.0
+    """max |F_gpu - F_oracle| over all E and B components, relative to the
+    largest field magnitude (components that vanish exactly in the oracle,
+    such as B_z of a plane wave, carry only rounding on the GPU)."""
+    diff, scale = 0.0, 1e-300
     for c in range(6):
         g = run.field(c)
         o = st.field(c)
-        scale = max(np.abs(o).max(), 1e-30)
-        worst = max(worst, np.abs(g - o).max() / scale)
-    return worst
+        scale = max(scale, np.abs(o).max())
+        diff = max(diff, np.abs(g - o).max())
+    return diff / scale
 
 
 def _small3d(**over):
@@ -199,11 +202,18 @@ def test_no_plasma_and_no_laser_edge_cases():
     r.close()
     cfg = workloads.config("c1", nz=32, nx=16, a0=0.0)
     r = pic.Run(cfg, "fp32")
+    st = oracle.State(cfg, round_f32=True)
+    assert r.diag()["n_particles"] == 32 * 16 * 4
     r.step(5)
+    st.step(5)
     d = r.diag()
-    assert d["n_particles"] == 32 * 16 * 4
-    assert d["Ez_max"] < 1e-3
+    # electrons leave through z = 0 and enter from the reservoir; E_z is the
+    # field of the current noise of the randomly placed drifting electrons
+    do = st.diag()
+    assert d["n_particles"] == do["n_particles"]
+    assert d["Ez_max"] == pytest.approx(do["Ez_max"], rel=1e-3)
     r.close()
+    st.close()
 
 
 def test_boris_option_matches_oracle_boris():

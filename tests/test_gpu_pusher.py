@@ -1,0 +1,74 @@
+"""GPU pusher microbenchmark kernel (pic_push_bench) against the oracle's
+pushers: per-particle uniform fields, positions on a unit grid."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_0909_5603_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_0909_5603_amd import pic  # noqa: E402
+
+
+def _gpu_push(prec, pusher, u, Ex, B, cell, off, nsteps, dt=workloads.PUSH_DT):
+    dtype = torch.float64 if prec == pic.PIC_FP64 else torch.float32
+    n = u.shape[0]
+    dev = "cuda"
+    tu = torch.tensor(np.ascontiguousarray(u.T).ravel(), dtype=dtype, device=dev)
+    tE = torch.tensor(Ex, dtype=dtype, device=dev)
+    tc = torch.tensor(np.ascontiguousarray(cell.T).ravel(), dtype=torch.int32, device=dev)
+    to = torch.tensor(np.ascontiguousarray(off.T).ravel(), dtype=dtype, device=dev)
+    s = torch.cuda.current_stream()
+    pic.pic_push_bench(prec, pusher, n, nsteps, dt, B, tE.data_ptr(), tu.data_ptr(), tc.data_ptr(),
+                       to.data_ptr(), s.cuda_stream)
+    torch.cuda.synchronize()
+    uo = tu.double().cpu().numpy().reshape(3, n).T
+    pos = tc.double().cpu().numpy().reshape(3, n).T + to.double().cpu().numpy().reshape(3, n).T
+    return uo, pos
+
+
+@pytest.mark.parametrize("kind", ["crossed", "gyration"])
+@pytest.mark.parametrize("pusher", [pic.PIC_VAY, pic.PIC_BORIS])
+def test_fp64_push_bench_matches_oracle(kind, pusher):
+    n, nsteps = 4096, 100
+    u, Ex, B, cell, off = workloads.pusher_set(n, kind, seed=2)
+    ug, pg = _gpu_push(pic.PIC_FP64, pusher, u, Ex, B, cell, off, nsteps)
+    E = np.zeros((n, 3))
+    E[:, 0] = Ex
+    Bn = np.tile(B, (n, 1))
+    uo, po = oracle.push_many(u, E, Bn, cell + off, workloads.PUSH_DT, nsteps,
+                              oracle.BORIS if pusher == pic.PIC_BORIS else oracle.VAY)
+    rel = np.linalg.norm(ug - uo, axis=1) / np.linalg.norm(uo, axis=1)
+    assert rel.max() < 1e-10
+    assert np.abs(pg - po).max() < 1e-8
+
+
+def test_fp32_split_push_cancellation_and_gamma_drift():
+    """Split precision with the FP64 gamma solve: crossed fields stay on the
+    straight line and gyration conserves gamma up to gamma = 1e6.  Crossed
+    fields: a random walk of half an FP32 ulp per step over 200 steps, with
+    margin (sqrt(200) 2^-24 ~ 8e-7).  Gyration: at gamma ~ 1e5 the rotation per
+    step (|eps B|/gamma ~ 3e-7 rad) is below the FP32 resolution of the
+    stored momentum, so each component can be rounded by up to one ulp per
+    step in the same direction: N 2^-23 = 2.4e-5 for N = 200."""
+    n, nsteps = 8192, 200
+    u, Ex, B, cell, off = workloads.pusher_set(n, "crossed", seed=2)
+    ug, pg = _gpu_push(pic.PIC_FP32_SPLIT, pic.PIC_VAY, u, Ex, B, cell, off, nsteps)
+    u32 = u.astype(np.float32).astype(np.float64)
+    cancel = np.linalg.norm(ug - u32, axis=1) / np.linalg.norm(u32, axis=1)
+    assert cancel.max() < 3e-6
+    assert (np.abs(ug[:, 0]) / np.linalg.norm(ug, axis=1)).max() < 1e-6
+    u, Ex, B, cell, off = workloads.pusher_set(n, "gyration", seed=3)
+    ug, _ = _gpu_push(pic.PIC_FP32_SPLIT, pic.PIC_VAY, u, Ex, B, cell, off, nsteps)
+    g0 = np.sqrt(1 + (u.astype(np.float32).astype(np.float64) ** 2).sum(1))
+    g1 = np.sqrt(1 + (ug ** 2).sum(1))
+    assert (np.abs(g1 - g0) / g0).max() < 1.5 * nsteps * 2.0**-23
+    E = np.zeros((n, 3))
+    uo, _ = oracle.push_many(u, E, np.tile(B, (n, 1)), cell + off, workloads.PUSH_DT, nsteps)
+    rel = np.linalg.norm(ug - uo, axis=1) / np.linalg.norm(uo, axis=1)
+    assert rel.max() < 1e-4
