@@ -62,8 +62,10 @@ def run_main(cfg, precision, steps, warmup, pic, torch):
     sec = t1 - t0
     out = {"ms_per_step": 1e3 * sec / steps, "value": n_box * steps / sec, "n_box": n_box,
            "diag": {k: d1[k] for k in ("step", "U_E", "U_B", "Ez_max", "KE", "n_particles",
-                                       "gauss_drift", "err_bits")}}
-    log(f"[{precision}] {out['ms_per_step']:.3f} ms/step, {out['value']:.3e} particle-steps/s")
+                                       "gauss_drift", "err_bits")},
+           "slow_path_fraction": d1["n_slow"] / max(1.0, n_box * (steps + warmup))}
+    log(f"[{precision}] {out['ms_per_step']:.3f} ms/step, {out['value']:.3e} particle-steps/s, "
+        f"slow-path fraction {out['slow_path_fraction']:.2e}")
     return run, out
 
 
@@ -161,6 +163,7 @@ def main():
     ms, roof = kernel_roofline(run, pic, args.timing_steps)
     line["roofline"] = roof
     line["diag_fp32"] = r32["diag"]
+    line["slow_path_fraction"] = r32["slow_path_fraction"]
     log(f"[fp32] stage ms/step: {ms}; particle kernel {roof['achieved']:.0f} GB/s "
         f"({100 * roof['frac']:.1f}% of HBM peak)")
     run.close()

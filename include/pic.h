@@ -100,6 +100,8 @@ typedef struct {
                             (needs PIC_DIAGF_CONTINUITY, else -1) */
   double gauss_drift;    /* max |(divE-rho)^n-(divE-rho)^0| / max|rho_e^0| */
   uint32_t err_bits;     /* device error word */
+  int64_t n_slow;        /* particle pushes since the last call whose stencil left
+                            the tile's LDS window (they read and deposit in HBM) */
 } pic_diag_out;
 
 enum { PIC_DIAG_FIELDS = 1u, PIC_DIAG_PARTICLES = 2u, PIC_DIAG_GAUSS = 4u, PIC_DIAG_ALL = 7u };

@@ -227,12 +227,30 @@ __device__ __forceinline__ double div_e(const RunDev& rd, R* const* F, int k, in
          (ev(rd, F, 2, k, i, j) - ev(rd, F, 2, k - 1, i, j)) * idz;
 }
 
+// divergence of the fixed-point current at node (k,i,j), in units of 1/jscale
+__device__ __forceinline__ double jv(const RunDev& rd, const long long* const* J, int c, int k, int i, int j) {
+  i = wrapi(i, rd.nx);
+  j = rd.dims == 3 ? wrapi(j, rd.ny) : 0;
+  if (rd.open) {
+    if (k < 0 || k >= zcount(rd, c)) return 0.0;
+  } else {
+    k = wrapi(k, rd.nz);
+  }
+  return (double)J[c][gidx(rd, k, i, j)];
+}
+__device__ __forceinline__ double div_j(const RunDev& rd, const long long* const* J, int k, int i, int j) {
+  const double idz = 1.0 / rd.dz, idx = 1.0 / rd.dx, idy = rd.dims == 3 ? 1.0 / rd.dy : 0.0;
+  return (jv(rd, J, 0, k, i, j) - jv(rd, J, 0, k, i - 1, j)) * idx +
+         (jv(rd, J, 1, k, i, j) - jv(rd, J, 1, k, i, j - 1)) * idy +
+         (jv(rd, J, 2, k, i, j) - jv(rd, J, 2, k - 1, i, j)) * idz;
+}
+
 // continuity residual |rho_b - rho_a + dt div J| and |rho_a| maxima (interior nodes)
 template <typename R>
 __global__ __launch_bounds__(256) void k_cont(const RunDev* __restrict__ rdp) {
   __shared__ double sh[4];
   const RunDev& rd = *rdp;
-  R* const* J = reinterpret_cast<R* const*>(rd.J[rd.ctr->fbuf]);
+  const long long* const* J = reinterpret_cast<const long long* const*>(rd.J[rd.ctr->fbuf]);
   double res = 0.0, rmax = 0.0;
   for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < rd.npts;
        q += (long long)gridDim.x * blockDim.x) {
@@ -241,7 +259,7 @@ __global__ __launch_bounds__(256) void k_cont(const RunDev* __restrict__ rdp) {
     const int i = (int)(t % rd.nx), j = (int)(t / rd.nx);
     if (rd.open && k > rd.nz) continue;
     if (!interior(rd, 0, k)) continue;
-    const double d = rd.rho_b[q] - rd.rho_a[q] + rd.dt * div_e(rd, J, k, i, j);
+    const double d = rd.rho_b[q] - rd.rho_a[q] + rd.dt * rd.jinv * div_j(rd, J, k, i, j);
     res = fmax(res, fabs(d));
     rmax = fmax(rmax, fabs(rd.rho_a[q]));
   }
@@ -268,7 +286,8 @@ __global__ void k_jlast(const RunDev* __restrict__ rdp) {
   const RunDev& rd = *rdp;
   for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < rd.npts;
        q += (long long)gridDim.x * blockDim.x)
-    for (int c = 0; c < 3; ++c) rd.jlast[c][q] = (double)fptr<R>(rd.J[rd.ctr->fbuf][c])[q];
+    for (int c = 0; c < 3; ++c)
+      rd.jlast[c][q] = (double)reinterpret_cast<const long long*>(rd.J[rd.ctr->fbuf][c])[q] * rd.jinv;
 }
 
 // ------------------------------------------------------------------ Gauss

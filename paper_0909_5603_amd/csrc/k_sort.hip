@@ -86,11 +86,15 @@ __global__ __launch_bounds__(256) void k_inject(const BatchTable* __restrict__ b
         atomicOr(&rd.ctr->err, 2u);
         break;
       }
+      // slot outermost within a column: consecutive new particles lie in
+      // consecutive cells, so the lanes of a wavefront deposit to different
+      // LDS addresses; the lattice id does not depend on this order
       const long long K = c.next_col + q / per_col;
       const long long rem = q % per_col;
-      const long long cperp = rem / rd.ppc;
+      const long long sl = rem / rd.nperp;
+      const long long cperp = rem % rd.nperp;
       const int i = (int)(cperp % rd.nx), j = (int)(cperp / rd.nx);
-      const uint64_t L = (uint64_t)(c.next_col * per_col + q);
+      const uint64_t L = (uint64_t)((K * rd.nperp + cperp) * rd.ppc + sl);
       uint64_t a[4] = {L, 0, 0, 0}, b[4] = {L, 1, 0, 0};
       philox4x64_10(a, rd.seed, 0);
       philox4x64_10(b, rd.seed, 0);

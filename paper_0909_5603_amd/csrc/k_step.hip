@@ -8,8 +8,10 @@
 //   gather (linear interpolation at each component's Yee stagger),
 //   push (modified Lorentz force with analytic gamma, Vay 2008),
 //   move (int cell + in-cell offset, one carry per dimension),
-//   deposit (Esirkepov 2001, linear shape, into LDS with ds_add),
-// and flushes the window's current to HBM with global atomics.  The window
+//   deposit (Esirkepov 2001, linear shape, into LDS in 64-bit fixed point
+//   with ds_add_u64: the integer LDS atomics run ~30x faster than ds_add_f32
+//   on gfx950 and make the sum independent of the order of the particles),
+// and flushes the window's current to HBM with 64-bit integer atomics.  The window
 // follows the bounding box of the tile's particles measured in the previous
 // step, so it tracks the plasma as it streams through the boosted frame.
 // Particles whose stencil leaves the window take a slow path that reads and
@@ -122,117 +124,143 @@ __device__ __forceinline__ int carry(R& o) {
   return 0;
 }
 
-// charge-conserving current of one particle, linear shape (Esirkepov 2001).
-// add(comp, dk, di, dj, v) receives offsets from the particle's old cell.
-template <int DIM, typename R, class A>
-__device__ __forceinline__ void deposit(const Dep1<R>* d, R cz, R cx, R cy, R cyv, A&& add) {
-  const Dep1<R>& Z = d[0];
-  const Dep1<R>& X = d[1];
-  if constexpr (DIM == 3) {
-    const Dep1<R>& Y = d[2];
-    R Ay[3], By[3], Ax[3], Bx[3];
+// Charge-conserving current of one particle, linear shape (Esirkepov 2001),
+// factored as J = c P[a] F(b,c): P is the running sum of the shape change
+// along the current's direction and F the time-averaged shape across it.
+// Contributions are converted to 64-bit fixed point (to_fixed) and handed
+// to add(comp, dk, di, dj, q) with offsets from the particle's old cell.
+// NX, NY = nodes spanned across x and y: 3 when some lane of the wavefront
+// crossed a cell boundary in that dimension, otherwise 2 (the third node and
+// the second face carry exact zeros then and are not visited).
+template <typename R, int NX, int NY, class A>
+__device__ __forceinline__ void dep3(const Dep1<R>& Z, const Dep1<R>& X, const Dep1<R>& Y, double czS,
+                                     double cxS, double cyS, A&& add) {
+  R Ay[3], By[3], Ax[3], Bx[3];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      Ay[c] = Y.S0[c] + R(0.5) * Y.DS[c];
-      By[c] = R(0.5) * Y.S0[c] + R(1.0 / 3.0) * Y.DS[c];
-      Ax[c] = X.S0[c] + R(0.5) * X.DS[c];
-      Bx[c] = R(0.5) * X.S0[c] + R(1.0 / 3.0) * X.DS[c];
-    }
-    // J_z(face a; node b, c) = cz P_z[a] (S0x Ay + DSx By)
+  for (int c = 0; c < 3; ++c) {
+    Ay[c] = Y.S0[c] + R(0.5) * Y.DS[c];
+    By[c] = R(0.5) * Y.S0[c] + R(1.0 / 3.0) * Y.DS[c];
+    Ax[c] = X.S0[c] + R(0.5) * X.DS[c];
+    Bx[c] = R(0.5) * X.S0[c] + R(1.0 / 3.0) * X.DS[c];
+  }
+  // J_z(face a; node b, c) = cz P_z[a] (S0x Ay + DSx By)
 #pragma unroll
-    for (int b = 0; b < 3; ++b)
+  for (int b = 0; b < NX; ++b)
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const R f = X.S0[b] * Ay[c] + X.DS[b] * By[c];
-#pragma unroll
-        for (int a = 0; a < 2; ++a) {
-          const R v = cz * Z.P[a] * f;
-          if (v != R(0)) add(2, Z.base + a, X.base + b, Y.base + c, v);
-        }
-      }
-    // J_x(node a; face b; node c) = cx P_x[b] (S0z Ay + DSz By)
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const R f = Z.S0[a] * Ay[c] + Z.DS[a] * By[c];
-#pragma unroll
-        for (int b = 0; b < 2; ++b) {
-          const R v = cx * X.P[b] * f;
-          if (v != R(0)) add(0, Z.base + a, X.base + b, Y.base + c, v);
-        }
-      }
-    // J_y(node a, b; face c) = cy P_y[c] (S0z Ax + DSz Bx)
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-      for (int b = 0; b < 3; ++b) {
-        const R f = Z.S0[a] * Ax[b] + Z.DS[a] * Bx[b];
-#pragma unroll
-        for (int c = 0; c < 2; ++c) {
-          const R v = cy * Y.P[c] * f;
-          if (v != R(0)) add(1, Z.base + a, X.base + b, Y.base + c, v);
-        }
-      }
-  } else {
-    R Ax[3], Bx[3];
-#pragma unroll
-    for (int b = 0; b < 3; ++b) {
-      Ax[b] = X.S0[b] + R(0.5) * X.DS[b];
-      Bx[b] = R(0.5) * X.S0[b] + R(1.0 / 3.0) * X.DS[b];
-    }
-    // J_z(face a; node b) = cz P_z[a] (S0x + DSx/2)
-#pragma unroll
-    for (int b = 0; b < 3; ++b)
+    for (int c = 0; c < NY; ++c) {
+      const R f = X.S0[b] * Ay[c] + X.DS[b] * By[c];
 #pragma unroll
       for (int a = 0; a < 2; ++a) {
-        const R v = cz * Z.P[a] * Ax[b];
-        if (v != R(0)) add(2, Z.base + a, X.base + b, 0, v);
-      }
-    // J_x(node a; face b) = cx P_x[b] (S0z + DSz/2)
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      const R az = Z.S0[a] + R(0.5) * Z.DS[a];
-#pragma unroll
-      for (int b = 0; b < 2; ++b) {
-        const R v = cx * X.P[b] * az;
-        if (v != R(0)) add(0, Z.base + a, X.base + b, 0, v);
+        const long long q = to_fixed(Z.P[a] * f, czS);
+        if (q != 0) add(2, Z.base + a, X.base + b, Y.base + c, q);
       }
     }
-    // J_y(node a, b) = cyv * time-averaged shape
+  // J_x(node a; face b; node c) = cx P_x[b] (S0z Ay + DSz By)
 #pragma unroll
-    for (int a = 0; a < 3; ++a)
+  for (int a = 0; a < 3; ++a)
 #pragma unroll
-      for (int b = 0; b < 3; ++b) {
-        const R v = cyv * (Z.S0[a] * Ax[b] + Z.DS[a] * Bx[b]);
-        if (v != R(0)) add(1, Z.base + a, X.base + b, 0, v);
+    for (int c = 0; c < NY; ++c) {
+      const R f = Z.S0[a] * Ay[c] + Z.DS[a] * By[c];
+#pragma unroll
+      for (int b = 0; b < NX - 1; ++b) {
+        const long long q = to_fixed(X.P[b] * f, cxS);
+        if (q != 0) add(0, Z.base + a, X.base + b, Y.base + c, q);
       }
+    }
+  // J_y(node a, b; face c) = cy P_y[c] (S0z Ax + DSz Bx)
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < NX; ++b) {
+      const R f = Z.S0[a] * Ax[b] + Z.DS[a] * Bx[b];
+#pragma unroll
+      for (int c = 0; c < NY - 1; ++c) {
+        const long long q = to_fixed(Y.P[c] * f, cyS);
+        if (q != 0) add(1, Z.base + a, X.base + b, Y.base + c, q);
+      }
+    }
+}
+
+// 2D3V: J_z = cz P_z (S0x + DSx/2), J_x = cx P_x (S0z + DSz/2), and the
+// out-of-plane J_y = q w v_y times the time-averaged node shape.
+template <typename R, int NX, class A>
+__device__ __forceinline__ void dep2(const Dep1<R>& Z, const Dep1<R>& X, double czS, double cxS,
+                                     double cyvS, A&& add) {
+  R Ax[3], Bx[3];
+#pragma unroll
+  for (int b = 0; b < 3; ++b) {
+    Ax[b] = X.S0[b] + R(0.5) * X.DS[b];
+    Bx[b] = R(0.5) * X.S0[b] + R(1.0 / 3.0) * X.DS[b];
+  }
+#pragma unroll
+  for (int b = 0; b < NX; ++b)
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      const long long q = to_fixed(Z.P[a] * Ax[b], czS);
+      if (q != 0) add(2, Z.base + a, X.base + b, 0, q);
+    }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const R az = Z.S0[a] + R(0.5) * Z.DS[a];
+#pragma unroll
+    for (int b = 0; b < NX - 1; ++b) {
+      const long long q = to_fixed(X.P[b] * az, cxS);
+      if (q != 0) add(0, Z.base + a, X.base + b, 0, q);
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < NX; ++b) {
+      const long long q = to_fixed(Z.S0[a] * Ax[b] + Z.DS[a] * Bx[b], cyvS);
+      if (q != 0) add(1, Z.base + a, X.base + b, 0, q);
+    }
+}
+
+template <int DIM, typename R, class A>
+__device__ __forceinline__ void deposit(const Dep1<R>* d, const int* cr, double czS, double cxS,
+                                        double cyS, double cyvS, A&& add) {
+  // wavefront-uniform: does any active lane cross a cell boundary in x / y?
+  const bool anyx = __any(cr[1] != 0);
+  if constexpr (DIM == 3) {
+    const bool anyy = __any(cr[2] != 0);
+    if (anyx) {
+      if (anyy) dep3<R, 3, 3>(d[0], d[1], d[2], czS, cxS, cyS, add);
+      else dep3<R, 3, 2>(d[0], d[1], d[2], czS, cxS, cyS, add);
+    } else {
+      if (anyy) dep3<R, 2, 3>(d[0], d[1], d[2], czS, cxS, cyS, add);
+      else dep3<R, 2, 2>(d[0], d[1], d[2], czS, cxS, cyS, add);
+    }
+  } else {
+    if (anyx) dep2<R, 3>(d[0], d[1], czS, cxS, cyvS, add);
+    else dep2<R, 2>(d[0], d[1], czS, cxS, cyvS, add);
   }
 }
 
-// E value with HBM index handling (zero outside an open z range)
+// E value with HBM index handling (zero outside an open z range).  Indices
+// are at most a few cells outside the box, so one correction wraps them.
 template <int DIM, typename R>
 __device__ __forceinline__ R gE(const RunDev& rd, R* const* E, int comp, int k, int i, int j) {
-  i = wrapi(i, rd.nx);
-  j = DIM == 3 ? wrapi(j, rd.ny) : 0;
+  i = wrap1(i, rd.nx);
+  j = DIM == 3 ? wrap1(j, rd.ny) : 0;
   if (rd.open) {
     if (k < 0 || k >= zcount(rd, comp)) return R(0);
   } else {
-    k = wrapi(k, rd.nz);
+    k = wrap1(k, rd.nz);
   }
   return E[comp][gidx(rd, k, i, j)];
 }
 
-// field value at integer time n for the slow path: E directly, B advanced
+// field value at integer time n for the HBM path: E directly, B advanced
 // from n-1/2 on the fly
 template <int DIM, typename R>
 __device__ R fetch_hbm(const RunDev& rd, R* const* E, R* const* B, int comp, int k, int i, int j) {
   if (comp < 3) return gE<DIM, R>(rd, E, comp, k, i, j);
-  int ii = wrapi(i, rd.nx), jj = DIM == 3 ? wrapi(j, rd.ny) : 0, kk = k;
+  int ii = wrap1(i, rd.nx), jj = DIM == 3 ? wrap1(j, rd.ny) : 0, kk = k;
   if (rd.open) {
     if (k < 0 || k >= zcount(rd, comp)) return R(0);
   } else {
-    kk = wrapi(k, rd.nz);
+    kk = wrap1(k, rd.nz);
   }
   const R b = B[comp - 3][gidx(rd, kk, ii, jj)];
   const R idz = R(1.0 / rd.dz), idx = R(1.0 / rd.dx), idy = DIM == 3 ? R(1.0 / rd.dy) : R(0);
@@ -249,26 +277,114 @@ __device__ R fetch_hbm(const RunDev& rd, R* const* E, R* const* B, int comp, int
   return b - R(0.5 * rd.dt) * curl;
 }
 
-template <int DIM, typename R>
-__device__ __forceinline__ void add_hbm(const RunDev& rd, int fb, int comp, int k, int i, int j, R v) {
-  i = wrapi(i, rd.nx);
-  j = DIM == 3 ? wrapi(j, rd.ny) : 0;
+template <int DIM>
+__device__ __forceinline__ void add_hbm(const RunDev& rd, int fb, int comp, int k, int i, int j, long long q) {
+  i = wrap1(i, rd.nx);
+  j = DIM == 3 ? wrap1(j, rd.ny) : 0;
   if (rd.open) {
     if (k < 0 || k >= zcount(rd, comp)) return;  // current outside the box is dropped
   } else {
-    k = wrapi(k, rd.nz);
+    k = wrap1(k, rd.nz);
   }
-  atomicAdd(fptr<R>(rd.J[fb][comp]) + gidx(rd, k, i, j), v);
+  atomicAdd(reinterpret_cast<unsigned long long*>(rd.J[fb][comp]) + gidx(rd, k, i, j),
+            (unsigned long long)q);
 }
 
 // ------------------------------------------------------------------ particles
+// constants of the particle update
+template <typename R>
+struct PConst {
+  R eps, cdz, cdx, cdy;
+  double czS, cxS, cyS, cyvS;  // current coefficients times the fixed-point scale
+};
+
+template <int DIM, typename R>
+__device__ __forceinline__ PConst<R> pconst(const RunDev& rd) {
+  PConst<R> K;
+  K.eps = R(-0.5 * rd.dt);
+  K.cdz = R(rd.dt / rd.dz);
+  K.cdx = R(rd.dt / rd.dx);
+  K.cdy = R(rd.dt / rd.dy);
+  const double S = rd.jscale;
+  if (DIM == 3) {
+    K.czS = S * rd.weight / (rd.dx * rd.dy * rd.dt);
+    K.cxS = S * rd.weight / (rd.dz * rd.dy * rd.dt);
+    K.cyS = S * rd.weight / (rd.dz * rd.dx * rd.dt);
+  } else {
+    K.czS = S * rd.weight / (rd.dx * rd.dt);
+    K.cxS = S * rd.weight / (rd.dz * rd.dt);
+    K.cyS = 0.0;
+  }
+  K.cyvS = -S * rd.weight / (rd.dz * rd.dx);
+  return K;
+}
+
+// Gather, push, move and deposit of one particle.  o[] holds the old
+// offsets on entry and the new ones on exit, cr[] receives the cell carries.
+// fetch(comp, dk, di, dj) and add(comp, dk, di, dj, v) address fields and
+// currents relative to the particle's old cell.  Returns true if the new
+// momentum is not finite.
+template <int DIM, typename R, int PUSHER, class F, class A>
+__device__ __forceinline__ bool advance(const PConst<R>& K, R* o, R& ux, R& uy, R& uz, int* cr,
+                                        F&& fetch, A&& add) {
+  W1<R> wt[3];
+  wt[0] = weights(o[0]);
+  wt[1] = weights(o[1]);
+  if (DIM == 3) wt[2] = weights(o[2]);
+  const R ex = interp<DIM, 0, R>(wt, fetch);
+  const R ey = interp<DIM, 1, R>(wt, fetch);
+  const R ez = interp<DIM, 2, R>(wt, fetch);
+  const R bx = interp<DIM, 3, R>(wt, fetch);
+  const R by = interp<DIM, 4, R>(wt, fetch);
+  const R bz = interp<DIM, 5, R>(wt, fetch);
+  if (PUSHER == 1)
+    push_boris<R>(ux, uy, uz, ex, ey, ez, bx, by, bz, K.eps);
+  else
+    push_vay<R>(ux, uy, uz, ex, ey, ez, bx, by, bz, K.eps);
+  const R g1 = sqrt(R(1) + ux * ux + uy * uy + uz * uz);
+  const bool bad = !(g1 < R(3.0e38));
+  const R ig = R(1) / g1;
+  R on[3];
+  on[0] = o[0] + K.cdz * uz * ig;
+  on[1] = o[1] + K.cdx * ux * ig;
+  on[2] = DIM == 3 ? o[2] + K.cdy * uy * ig : R(0);
+  cr[0] = carry(on[0]);
+  cr[1] = carry(on[1]);
+  cr[2] = DIM == 3 ? carry(on[2]) : 0;
+  Dep1<R> dd[3];
+  dd[0] = dep1(o[0], on[0], cr[0]);
+  dd[1] = dep1(o[1], on[1], cr[1]);
+  if (DIM == 3) dd[2] = dep1(o[2], on[2], cr[2]);
+  deposit<DIM, R>(dd, cr, K.czS, K.cxS, K.cyS, K.cyvS * (double)(uy * ig), add);
+  o[0] = on[0];
+  o[1] = on[1];
+  o[2] = on[2];
+  return bad;
+}
+
+// new packed cell after the carries; removal at the open z ends
+template <int DIM>
+__device__ __forceinline__ int new_cell(const RunDev& rd, int k, int i, int j, const int* cr, bool& dead,
+                                        int& k1, int& i1, int& j1) {
+  k1 = k + cr[0];
+  i1 = wrap1(i + cr[1], rd.nx);
+  j1 = DIM == 3 ? wrap1(j + cr[2], rd.ny) : 0;
+  dead = false;
+  if (rd.open)
+    dead = k1 < 0 || k1 >= rd.ztop;
+  else
+    k1 = wrap1(k1, rd.nz);
+  return cell_pack(k1, i1, j1) | (dead ? (int)DEAD : 0);
+}
+
 template <int DIM, typename R, int BLOCK, int PUSHER>
 __global__ __launch_bounds__(BLOCK) void k_particles(const BatchTable* __restrict__ bt) {
   using T = Tile<DIM>;
   constexpr int WZM = T::WZ, WXM = T::WX, WYM = T::WY;
   constexpr int WV = WZM * WXM * WYM;
   constexpr int SY = (DIM == 3) ? WZM * WXM : 0;  // LDS stride of y
-  __shared__ R sF[9][WV];  // Ex Ey Ez Bx By Bz Jx Jy Jz of the tile window
+  __shared__ R sF[6][WV];           // Ex Ey Ez Bx By Bz of the tile window
+  __shared__ long long sJ[3][WV];   // Jx Jy Jz, 64-bit fixed point
   __shared__ int sred[6][BLOCK / 64];
 
   const XcdSplit xs(bt->tiles);
@@ -324,8 +440,8 @@ __global__ __launch_bounds__(BLOCK) void k_particles(const BatchTable* __restric
       const int rx = t % Wd[1], ry = t / Wd[1];
       const int s = (ry * WXM + rx) * WZM + rz;
       const int gk = w0[0] + rz;
-      const int gi = wrapi(w0[1] + rx, nx);
-      const int gj = DIM == 3 ? wrapi(w0[2] + ry, ny) : 0;
+      const int gi = wrap2(w0[1] + rx, nx);
+      const int gj = DIM == 3 ? wrap2(w0[2] + ry, ny) : 0;
       bool zn = true, zh = true;
       int kk = gk;
       if (open) {
@@ -333,7 +449,7 @@ __global__ __launch_bounds__(BLOCK) void k_particles(const BatchTable* __restric
         zh = gk >= 0 && gk < nz;
         kk = min(max(gk, 0), nzf - 1);
       } else {
-        kk = wrapi(gk, nz);
+        kk = wrap2(gk, nz);
       }
       const long long g = ((long long)gj * nx + gi) * nzf + kk;
       const R ex = Eg[0][g], ey = Eg[1][g], ez = Eg[2][g];
@@ -344,9 +460,9 @@ __global__ __launch_bounds__(BLOCK) void k_particles(const BatchTable* __restric
       sF[3][s] = zh ? bx : R(0);
       sF[4][s] = zh ? by : R(0);
       sF[5][s] = zn ? bz : R(0);
-      sF[6][s] = R(0);
-      sF[7][s] = R(0);
-      sF[8][s] = R(0);
+      sJ[0][s] = 0;
+      sJ[1][s] = 0;
+      sJ[2][s] = 0;
     }
     __syncthreads();
     // ---- B^n = B^{n-1/2} - dt/2 curl E^n on the window (last layer unused)
@@ -376,7 +492,8 @@ __global__ __launch_bounds__(BLOCK) void k_particles(const BatchTable* __restric
     }
     __syncthreads();
 
-    // ---- particles
+    // ---- particles whose stencil lies in the window; the others are queued
+    // for the HBM kernel
     int* __restrict__ cellp = rd.cell[pb];
     R* __restrict__ o0p = fptr<R>(rd.off[pb][0]);
     R* __restrict__ o1p = fptr<R>(rd.off[pb][1]);
@@ -384,21 +501,8 @@ __global__ __launch_bounds__(BLOCK) void k_particles(const BatchTable* __restric
     R* __restrict__ uxp = fptr<R>(rd.u[pb][0]);
     R* __restrict__ uyp = fptr<R>(rd.u[pb][1]);
     R* __restrict__ uzp = fptr<R>(rd.u[pb][2]);
-    const R eps = R(-0.5) * dt;
-    const R cdz = R(rd.dt / rd.dz), cdx = R(rd.dt / rd.dx), cdy = R(rd.dt / rd.dy);
-    const double wgt = rd.weight;
-    R cz, cx, cy;
-    if (DIM == 3) {
-      cz = R(wgt / (rd.dx * rd.dy * rd.dt));
-      cx = R(wgt / (rd.dz * rd.dy * rd.dt));
-      cy = R(wgt / (rd.dz * rd.dx * rd.dt));
-    } else {
-      cz = R(wgt / (rd.dx * rd.dt));
-      cx = R(wgt / (rd.dz * rd.dt));
-      cy = R(0);
-    }
-    const R cyv0 = R(-wgt / (rd.dz * rd.dx));
-    const int gz = rd.gz, gx = rd.gx, gy = rd.gy, ztop = rd.ztop;
+    const PConst<R> K = pconst<DIM, R>(rd);
+    const int gz = rd.gz, gx = rd.gx, gy = rd.gy;
     int bmin0 = 1 << 20, bmin1 = 1 << 20, bmin2 = 1 << 20;
     int bmax0 = -(1 << 20), bmax1 = -(1 << 20), bmax2 = -(1 << 20);
     bool bad = false;
@@ -413,97 +517,43 @@ __global__ __launch_bounds__(BLOCK) void k_particles(const BatchTable* __restric
       const int wk = rk - lo[0] + 1, wi = ri - lo[1] + 1, wj = DIM == 3 ? rj - lo[2] + 1 : 0;
       const bool fast = wk >= 1 && wk <= Wd[0] - 3 && wi >= 1 && wi <= Wd[1] - 3 &&
                         (DIM == 2 || (wj >= 1 && wj <= Wd[2] - 3));
+      if (!fast) {
+        const unsigned e = atomicAdd(&rd.ctr->n_slowq, 1u);
+        if (e < (unsigned long long)rd.capacity) rd.slowq[e] = (int)p;
+        continue;
+      }
       R o[3];
       o[0] = o0p[p];
       o[1] = o1p[p];
       o[2] = DIM == 3 ? o2p[p] : R(0);
       R ux = uxp[p], uy = uyp[p], uz = uzp[p];
-      W1<R> wt[3];
-      wt[0] = weights(o[0]);
-      wt[1] = weights(o[1]);
-      if (DIM == 3) wt[2] = weights(o[2]);
-      R ex, ey, ez, bx, by, bz;
       const int base = (wj * WXM + wi) * WZM + wk;
-      if (fast) {
-        auto f = [&](int comp, int dk, int di, int dj) -> R {
-          return sF[comp][base + dk + di * WZM + dj * SY];
-        };
-        ex = interp<DIM, 0, R>(wt, f);
-        ey = interp<DIM, 1, R>(wt, f);
-        ez = interp<DIM, 2, R>(wt, f);
-        bx = interp<DIM, 3, R>(wt, f);
-        by = interp<DIM, 4, R>(wt, f);
-        bz = interp<DIM, 5, R>(wt, f);
-      } else {
-        auto f = [&](int comp, int dk, int di, int dj) -> R {
-          return fetch_hbm<DIM, R>(rd, Eg, Bg, comp, k + dk, i + di, j + dj);
-        };
-        ex = interp<DIM, 0, R>(wt, f);
-        ey = interp<DIM, 1, R>(wt, f);
-        ez = interp<DIM, 2, R>(wt, f);
-        bx = interp<DIM, 3, R>(wt, f);
-        by = interp<DIM, 4, R>(wt, f);
-        bz = interp<DIM, 5, R>(wt, f);
-      }
-      if (PUSHER == 1)
-        push_boris<R>(ux, uy, uz, ex, ey, ez, bx, by, bz, eps);
-      else
-        push_vay<R>(ux, uy, uz, ex, ey, ez, bx, by, bz, eps);
-      const R g1 = sqrt(R(1) + ux * ux + uy * uy + uz * uz);
-      bad |= !(g1 < R(3.0e38));
-      const R ig = R(1) / g1;
-      R on[3];
-      on[0] = o[0] + cdz * uz * ig;
-      on[1] = o[1] + cdx * ux * ig;
-      on[2] = DIM == 3 ? o[2] + cdy * uy * ig : R(0);
       int cr[3];
-      cr[0] = carry(on[0]);
-      cr[1] = carry(on[1]);
-      cr[2] = DIM == 3 ? carry(on[2]) : 0;
-      Dep1<R> dd[3];
-      dd[0] = dep1(o[0], on[0], cr[0]);
-      dd[1] = dep1(o[1], on[1], cr[1]);
-      if (DIM == 3) dd[2] = dep1(o[2], on[2], cr[2]);
-      const R cyv = cyv0 * uy * ig;
-      if (fast) {
-        deposit<DIM, R>(dd, cz, cx, cy, cyv, [&](int comp, int dk, int di, int dj, R v) {
-          atomicAdd(&sF[6 + comp][base + dk + di * WZM + dj * SY], v);
-        });
-      } else {
-        deposit<DIM, R>(dd, cz, cx, cy, cyv, [&](int comp, int dk, int di, int dj, R v) {
-          add_hbm<DIM, R>(rd, fb, comp, k + dk, i + di, j + dj, v);
-        });
-      }
-      int k1 = k + cr[0];
-      int i1 = i + cr[1];
-      i1 = i1 < 0 ? i1 + nx : (i1 >= nx ? i1 - nx : i1);
-      int j1 = 0;
-      if (DIM == 3) {
-        j1 = j + cr[2];
-        j1 = j1 < 0 ? j1 + ny : (j1 >= ny ? j1 - ny : j1);
-      }
-      bool dead = false;
-      if (open) {
-        dead = k1 < 0 || k1 >= ztop;
-      } else {
-        k1 = k1 < 0 ? k1 + nz : (k1 >= nz ? k1 - nz : k1);
-      }
-      cellp[p] = cell_pack(k1, i1, j1) | (dead ? (int)DEAD : 0);
-      o0p[p] = on[0];
-      o1p[p] = on[1];
-      if (DIM == 3) o2p[p] = on[2];
+      bad |= advance<DIM, R, PUSHER>(
+          K, o, ux, uy, uz, cr,
+          [&](int comp, int dk, int di, int dj) -> R { return sF[comp][base + dk + di * WZM + dj * SY]; },
+          [&](int comp, int dk, int di, int dj, long long q) {
+            atomicAdd(reinterpret_cast<unsigned long long*>(&sJ[comp][base + dk + di * WZM + dj * SY]),
+                      (unsigned long long)q);
+          });
+      bool dead;
+      int k1, i1, j1;
+      cellp[p] = new_cell<DIM>(rd, k, i, j, cr, dead, k1, i1, j1);
+      o0p[p] = o[0];
+      o1p[p] = o[1];
+      if (DIM == 3) o2p[p] = o[2];
       uxp[p] = ux;
       uyp[p] = uy;
       uzp[p] = uz;
       if (!dead) {
-        const int nk = open ? k1 - t0[0] : relw(k1, t0[0], nz, gz);
-        const int ni = relw(i1, t0[1], nx, gx);
+        const int nk = rk + cr[0];
+        const int ni = ri + cr[1];
         bmin0 = min(bmin0, nk);
         bmax0 = max(bmax0, nk);
         bmin1 = min(bmin1, ni);
         bmax1 = max(bmax1, ni);
         if (DIM == 3) {
-          const int nj = relw(j1, t0[2], ny, gy);
+          const int nj = rj + cr[2];
           bmin2 = min(bmin2, nj);
           bmax2 = max(bmax2, nj);
         }
@@ -543,22 +593,94 @@ __global__ __launch_bounds__(BLOCK) void k_particles(const BatchTable* __restric
       const int t = q / Wd[0];
       const int rx = t % Wd[1], ry = t / Wd[1];
       const int s = (ry * WXM + rx) * WZM + rz;
-      const R jx = sF[6][s], jy = sF[7][s], jz = sF[8][s];
-      if (jx == R(0) && jy == R(0) && jz == R(0)) continue;
+      const long long jx = sJ[0][s], jy = sJ[1][s], jz = sJ[2][s];
+      if ((jx | jy | jz) == 0) continue;
       int gk = w0[0] + rz;
-      const int gi = wrapi(w0[1] + rx, nx);
-      const int gj = DIM == 3 ? wrapi(w0[2] + ry, ny) : 0;
+      const int gi = wrap2(w0[1] + rx, nx);
+      const int gj = DIM == 3 ? wrap2(w0[2] + ry, ny) : 0;
       bool zn = true, zh = true;
       if (open) {
         zn = gk >= 0 && gk <= nz;
         zh = gk >= 0 && gk < nz;
       } else {
-        gk = wrapi(gk, nz);
+        gk = wrap2(gk, nz);
       }
       const long long g = ((long long)gj * nx + gi) * nzf + gk;
-      if (zn && jx != R(0)) atomicAdd(fptr<R>(rd.J[fb][0]) + g, jx);
-      if (zn && jy != R(0)) atomicAdd(fptr<R>(rd.J[fb][1]) + g, jy);
-      if (zh && jz != R(0)) atomicAdd(fptr<R>(rd.J[fb][2]) + g, jz);
+      unsigned long long* const* Jg = reinterpret_cast<unsigned long long* const*>(rd.J[fb]);
+      if (zn && jx != 0) atomicAdd(Jg[0] + g, (unsigned long long)jx);
+      if (zn && jy != 0) atomicAdd(Jg[1] + g, (unsigned long long)jy);
+      if (zh && jz != 0) atomicAdd(Jg[2] + g, (unsigned long long)jz);
+    }
+  }
+}
+
+// Particles whose stencil left their tile's window: gather from and deposit
+// into HBM directly, then widen the tile's bounding box.  Normally a tiny
+// queue (empty in the steady boosted-frame flow).
+template <int DIM, typename R, int PUSHER>
+__global__ __launch_bounds__(256) void k_particles_hbm(const BatchTable* __restrict__ bt) {
+  using T = Tile<DIM>;
+  for (int r = 0; r < bt->n; ++r) {
+    const RunDev& rd = *bt->run[r];
+    const Counters& ctr = *rd.ctr;
+    const long long n = min((long long)ctr.n_slowq, rd.capacity);
+    if (n == 0) continue;
+    const int pb = ctr.pbuf, fb = ctr.fbuf, bb = ctr.bbuf;
+    R* const* Eg = reinterpret_cast<R* const*>(rd.E[fb]);
+    R* const* Bg = reinterpret_cast<R* const*>(rd.B[fb]);
+    const PConst<R> K = pconst<DIM, R>(rd);
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+         e += (long long)gridDim.x * blockDim.x) {
+      const int p = rd.slowq[e];
+      const int c = rd.cell[pb][p];
+      const int k = cell_k(c), i = cell_i(c), j = DIM == 3 ? cell_j(c) : 0;
+      R o[3];
+      o[0] = fptr<R>(rd.off[pb][0])[p];
+      o[1] = fptr<R>(rd.off[pb][1])[p];
+      o[2] = DIM == 3 ? fptr<R>(rd.off[pb][2])[p] : R(0);
+      R ux = fptr<R>(rd.u[pb][0])[p], uy = fptr<R>(rd.u[pb][1])[p], uz = fptr<R>(rd.u[pb][2])[p];
+      int cr[3];
+      const bool bad = advance<DIM, R, PUSHER>(
+          K, o, ux, uy, uz, cr,
+          [&](int comp, int dk, int di, int dj) -> R {
+            return fetch_hbm<DIM, R>(rd, Eg, Bg, comp, k + dk, i + di, j + dj);
+          },
+          [&](int comp, int dk, int di, int dj, long long q) {
+            add_hbm<DIM>(rd, fb, comp, k + dk, i + di, j + dj, q);
+          });
+      if (bad) atomicOr(&rd.ctr->err, 1u);
+      bool dead;
+      int k1, i1, j1;
+      rd.cell[pb][p] = new_cell<DIM>(rd, k, i, j, cr, dead, k1, i1, j1);
+      fptr<R>(rd.off[pb][0])[p] = o[0];
+      fptr<R>(rd.off[pb][1])[p] = o[1];
+      if (DIM == 3) fptr<R>(rd.off[pb][2])[p] = o[2];
+      fptr<R>(rd.u[pb][0])[p] = ux;
+      fptr<R>(rd.u[pb][1])[p] = uy;
+      fptr<R>(rd.u[pb][2])[p] = uz;
+      if (!dead) {
+        // the tile of slot p: last tile whose start is <= p
+        int lo = 0, hi = rd.ntiles - 1;
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (rd.tile_start[mid] <= p) lo = mid; else hi = mid - 1;
+        }
+        const int tile = lo;
+        const int tz = tile % rd.ntz, rest = tile / rd.ntz;
+        const int tx = rest % rd.ntx, ty = rest / rd.ntx;
+        int* bbw = rd.bbox[bb ^ 1] + 6 * tile;
+        const int nk = rd.open ? k1 - tz * T::TZ : relw(k1, tz * T::TZ, rd.nz, rd.gz);
+        const int ni = relw(i1, tx * T::TX, rd.nx, rd.gx);
+        atomicMin(bbw + 0, nk);
+        atomicMax(bbw + 3, nk);
+        atomicMin(bbw + 1, ni);
+        atomicMax(bbw + 4, ni);
+        if (DIM == 3) {
+          const int nj = relw(j1, ty * T::TY, rd.ny, rd.gy);
+          atomicMin(bbw + 2, nj);
+          atomicMax(bbw + 5, nj);
+        }
+      }
     }
   }
 }
@@ -582,8 +704,9 @@ __global__ __launch_bounds__(256) void k_fields(const BatchTable* __restrict__ b
     R* const* Bm = reinterpret_cast<R* const*>(rd.B[fb]);
     R* const* En = reinterpret_cast<R* const*>(rd.E[fb ^ 1]);
     R* const* Bn = reinterpret_cast<R* const*>(rd.B[fb ^ 1]);
-    R* const* J = reinterpret_cast<R* const*>(rd.J[fb]);
-    R* const* Jnext = reinterpret_cast<R* const*>(rd.J[fb ^ 1]);
+    const long long* const* J = reinterpret_cast<const long long* const*>(rd.J[fb]);
+    long long* const* Jnext = reinterpret_cast<long long* const*>(rd.J[fb ^ 1]);
+    const double jinv = rd.jinv;
     const R dt = R(rd.dt);
     const R idz = R(1.0 / rd.dz), idx = R(1.0 / rd.dx), idy = DIM == 3 ? R(1.0 / rd.dy) : R(0);
 
@@ -619,7 +742,7 @@ __global__ __launch_bounds__(256) void k_fields(const BatchTable* __restrict__ b
     const long long g0 = ((long long)j * nx + i) * nzf;
     auto Jv = [&](int c, int kk) -> R {
       const int z = zk(c, kk);
-      return z < 0 ? R(0) : J[c][g0 + z];
+      return z < 0 ? R(0) : R((double)J[c][g0 + z] * jinv);
     };
     // E^{n+1} at (kk, i, j) from Ampere's law
     auto Enew = [&](int c, int kk) -> R {
@@ -652,9 +775,9 @@ __global__ __launch_bounds__(256) void k_fields(const BatchTable* __restrict__ b
     for (int c = 0; c < 3; ++c) Bn[c][g] = Bh(c, k, i, j);
     // the current read above (own point and, at the Mur ends, the next
     // interior point) stays intact; the buffer of the next step is cleared
-    Jnext[0][g] = R(0);
-    Jnext[1][g] = R(0);
-    Jnext[2][g] = R(0);
+    Jnext[0][g] = 0;
+    Jnext[1][g] = 0;
+    Jnext[2][g] = 0;
   }
 }
 
@@ -662,6 +785,8 @@ __global__ void k_advance(const BatchTable* __restrict__ bt) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= bt->n) return;
   Counters* c = bt->run[r]->ctr;
+  c->n_slow += c->n_slowq;
+  c->n_slowq = 0;
   c->step += 1;
   c->fbuf ^= 1;
   c->bbuf ^= 1;
@@ -675,11 +800,12 @@ struct PBlock {
 };
 
 int grid_particles(int dims, int prec, int ncu) {
+  const size_t per_cell = 6 * sizeof(float) * (prec ? 2 : 1) + 3 * sizeof(long long);
   size_t lds;
   if (dims == 3)
-    lds = 9 * sizeof(float) * (prec ? 2 : 1) * Tile<3>::WZ * Tile<3>::WX * Tile<3>::WY;
+    lds = per_cell * Tile<3>::WZ * Tile<3>::WX * Tile<3>::WY;
   else
-    lds = 9 * sizeof(float) * (prec ? 2 : 1) * Tile<2>::WZ * Tile<2>::WX;
+    lds = per_cell * Tile<2>::WZ * Tile<2>::WX;
   int per_cu = (int)((160 * 1024) / (lds + 1024));
   if (per_cu < 1) per_cu = 1;
   if (per_cu > 8) per_cu = 8;
@@ -692,10 +818,13 @@ int grid_generic(int ncu) { return ncu * 8; }
 template <int DIM, typename R>
 static void lp(int pusher, const BatchTable* bt, int grid, hipStream_t s) {
   constexpr int B = PBlock<DIM, R>::value;
-  if (pusher == 1)
+  if (pusher == 1) {
     hipLaunchKernelGGL((k_particles<DIM, R, B, 1>), dim3(grid), dim3(B), 0, s, bt);
-  else
+    hipLaunchKernelGGL((k_particles_hbm<DIM, R, 1>), dim3(1024), dim3(256), 0, s, bt);
+  } else {
     hipLaunchKernelGGL((k_particles<DIM, R, B, 0>), dim3(grid), dim3(B), 0, s, bt);
+    hipLaunchKernelGGL((k_particles_hbm<DIM, R, 0>), dim3(1024), dim3(256), 0, s, bt);
+  }
 }
 
 void launch_particles(int dims, int prec, int pusher, const BatchTable* bt, int grid, hipStream_t s) {

@@ -4,6 +4,7 @@
 // diagnostics and read-back.  See include/pic.h for the contract.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -55,7 +56,7 @@ struct Layout {
   size_t E[2][3], B[2][3], J[2][3];
   size_t cell[2], off[2][3], u[2][3], pid[2];
   size_t tile_start, tile_count, tile_cursor, bbox[2];
-  size_t rho_a, rho_b, gauss0, jlast[3], cell_snap;
+  size_t rho_a, rho_b, gauss0, jlast[3], cell_snap, slowq;
   size_t zero_end;  // [0, zero_end) is cleared at init
   size_t total;
 };
@@ -126,6 +127,15 @@ pic_status derive(const pic_lab_params* p, Derived& d) {
     d.max_new = (long long)p->nz * d.nperp * p->ppc;
   }
   if (d.capacity >= (1LL << 31) - 1) return fail(PIC_EINVAL, "too many particles for one run");
+  {
+    // one particle's current contribution is at most w / (dA dt); it must stay
+    // below 2^50 in the fixed-point units of the current (scale 2^32 or 2^40)
+    const double dA = p->dims == 3 ? std::min(p->dx * p->dy, std::min(p->dz * p->dy, p->dz * p->dx))
+                                   : std::min(p->dx, p->dz);
+    const double cmax = d.weight / (dA * d.dt) + d.weight / (p->dz * p->dx);
+    const double lim = p->precision == PIC_FP64 ? 1024.0 : 262144.0;
+    if (!(cmax < lim)) return fail(PIC_EINVAL, "current per particle %.3g exceeds the fixed-point range", cmax);
+  }
   d.rsz = p->precision == PIC_FP64 ? sizeof(double) : sizeof(float);
   return PIC_OK;
 }
@@ -148,7 +158,7 @@ void layout(const pic_lab_params* p, const Derived& d, Layout& L) {
   for (int b = 0; b < 2; ++b)
     for (int c = 0; c < 3; ++c) L.B[b][c] = take(fb);
   for (int b = 0; b < 2; ++b)
-    for (int c = 0; c < 3; ++c) L.J[b][c] = take(fb);
+    for (int c = 0; c < 3; ++c) L.J[b][c] = take(sizeof(long long) * d.npts);
   L.tile_start = take(sizeof(int) * (d.ntiles + 1));
   L.tile_count = take(sizeof(int) * d.ntiles);
   L.tile_cursor = take(sizeof(int) * d.ntiles);
@@ -162,6 +172,7 @@ void layout(const pic_lab_params* p, const Derived& d, Layout& L) {
   for (int c = 0; c < 3; ++c) L.jlast[c] = cont ? take(sizeof(double) * d.npts) : NOPT;
   L.cell_snap = cont ? take(sizeof(int) * d.capacity) : NOPT;
   const size_t cap = (size_t)d.capacity;
+  L.slowq = take(sizeof(int) * cap);
   for (int b = 0; b < 2; ++b) {
     L.cell[b] = take(sizeof(int) * cap);
     for (int c = 0; c < 3; ++c) L.off[b][c] = (c < p->dims) ? take(d.rsz * cap) : NOPT;
@@ -403,6 +414,10 @@ pic_status pic_init_boosted(const pic_lab_params* p, void* dev_buf, size_t bytes
   h.L_lab = d.L_lab;
   h.zc_boost = d.zc_boost;
   h.waist = r->p.waist;
+  // current in 64-bit fixed point: 2^-32 resolution for the split-precision
+  // path, 2^-40 for the FP64 path
+  h.jscale = r->p.precision == PIC_FP64 ? 1099511627776.0 : 4294967296.0;
+  h.jinv = 1.0 / h.jscale;
   h.seed = r->p.seed;
   const Layout& L = r->L;
   for (int b = 0; b < 2; ++b)
@@ -429,6 +444,7 @@ pic_status pic_init_boosted(const pic_lab_params* p, void* dev_buf, size_t bytes
   h.rho_b = at<double>(r, L.rho_b);
   h.gauss0 = at<double>(r, L.gauss0);
   h.cell_snap = at<int>(r, L.cell_snap);
+  h.slowq = at<int>(r, L.slowq);
   r->drd = at<RunDev>(r, L.rundev);
   r->dctr = at<Counters>(r, L.ctr);
   r->dtab1 = at<BatchTable>(r, L.tab1);
@@ -622,6 +638,8 @@ pic_status pic_diag(pic_run* r, unsigned what, pic_diag_out* out) {
     out->cont_resid = -1.0;
   }
   out->err_bits = c.err;
+  out->n_slow = (int64_t)c.n_slow;
+  HIPCHK(hipMemsetAsync(&r->dctr->n_slow, 0, sizeof(c.n_slow), s));
   if (c.err) {
     HIPCHK(hipStreamSynchronize(s));
     if (c.err & PIC_ERR_NAN) return fail(PIC_ESTATE, "device error: non-finite momentum");

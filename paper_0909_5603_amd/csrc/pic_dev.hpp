@@ -65,6 +65,9 @@ struct Counters {
   double acc[4];
   unsigned long long amax[4];
   unsigned long long cnt[2];
+  unsigned long long n_slow;  // particles that took the HBM path (since the last diag)
+  unsigned n_slowq;           // entries of this step's HBM-path queue
+  unsigned pad1;
 };
 
 struct RunDev {
@@ -76,13 +79,14 @@ struct RunDev {
   double dt, dz, dx, dy;
   double beta_b, gamma_b, dminus, dplus, weight, jion_z, rho_ion, u_th;
   double k0_lab, E0_lab, L_lab, zc_boost, waist;
+  double jscale, jinv;  // current stored as int64 = round(J * jscale)
   unsigned long long seed;
   // arrays (device addresses inside the caller's buffer); element type is
   // float (split-precision path) or double (FP64 path)
   void* E[2][3];
   void* B[2][3];  // B at half-integer time: B^{n-1/2} in B[fbuf]
-  void* J[2][3];  // the step deposits into J[fbuf]; the field kernel reads it
-                  // and clears J[fbuf^1] for the next step
+  void* J[2][3];  // int64 fixed point; the step deposits into J[fbuf], the
+                  // field kernel reads it and clears J[fbuf^1] for the next step
   int* cell[2];
   void* off[2][3];
   void* u[2][3];
@@ -96,6 +100,7 @@ struct RunDev {
   double* gauss0;
   double* jlast[3];
   int* cell_snap;
+  int* slowq;       // slots of particles deferred to the HBM path this step
   Counters* ctr;
 };
 
@@ -147,11 +152,18 @@ __device__ __forceinline__ int wrapi(int i, int n) {
   int r = i % n;
   return r < 0 ? r + n : r;
 }
-// tile-relative coordinate of a periodic index, in [-g, n-g)
+// periodic wrap of an index in [-n, 2n) (one correction)
+__device__ __forceinline__ int wrap1(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+// periodic wrap of an index in [-2n, 3n) (two corrections)
+__device__ __forceinline__ int wrap2(int i, int n) {
+  i = i < 0 ? i + n : (i >= n ? i - n : i);
+  return i < 0 ? i + n : (i >= n ? i - n : i);
+}
+// tile-relative coordinate of a periodic index i in [0,n) for a tile origin
+// t0 in [0,n) and a guard 0 <= g < n: result in [-g, n-g)
 __device__ __forceinline__ int relw(int i, int t0, int n, int g) {
   int r = i - t0 + g;
-  r %= n;
-  if (r < 0) r += n;
+  r = r < 0 ? r + n : (r >= n ? r - n : r);
   return r - g;
 }
 
@@ -187,6 +199,13 @@ __device__ __forceinline__ void philox4x64_10(uint64_t c[4], uint64_t k0, uint64
 }
 __device__ __forceinline__ double u01(uint64_t r) {
   return (double)(r >> 11) * (1.0 / 9007199254740992.0);
+}
+
+// x * scale rounded to the nearest integer as int64, for |x * scale| < 2^51:
+// adding 1.5 * 2^52 places the rounded integer in the low mantissa bits
+__device__ __forceinline__ long long to_fixed(double x, double scale) {
+  const double magic = 6755399441055744.0;  // 1.5 * 2^52
+  return __double_as_longlong(fma(x, scale, magic)) - 0x4338000000000000LL;
 }
 
 // bit pattern max for non-negative doubles

@@ -51,7 +51,8 @@ class pic_diag_out(ctypes.Structure):
     _fields_ = [("step", ctypes.c_int64), ("t", ctypes.c_double), ("U_E", ctypes.c_double),
                 ("U_B", ctypes.c_double), ("Ez_max", ctypes.c_double), ("KE", ctypes.c_double),
                 ("n_particles", ctypes.c_int64), ("cont_resid", ctypes.c_double),
-                ("gauss_drift", ctypes.c_double), ("err_bits", ctypes.c_uint32)]
+                ("gauss_drift", ctypes.c_double), ("err_bits", ctypes.c_uint32),
+                ("n_slow", ctypes.c_int64)]
 
 
 class pic_derived(ctypes.Structure):
