@@ -17,15 +17,13 @@
 // Particles whose stencil leaves the window take a slow path that reads and
 // deposits in HBM directly: results never depend on the window.
 //
-// Field kernel.  State is (E^n, B^{n-1/2}) in ping-pong buffers.  One thread
-// per grid point computes B^{n+1/2} = B^{n-1/2} - dt curl E^n for the four
-// B points its E update needs, then E^{n+1} = E^n + dt (curl B^{n+1/2} - J -
-// J_ion), and first-order Mur on the tangential E at open z ends.  The current
-// is double-buffered: the step deposits into J[fbuf], the field kernel reads
-// it (the Mur thread also reads its interior neighbour's) and clears the other
-// buffer, into which the next step deposits.  This is the standard leapfrog,
-// algebraically equal to two half steps of B around the E step with E and B
-// both at integer time.
+// Field update.  State is (E^n, B^{n-1/2}) in ping-pong buffers: B^{n+1/2} =
+// B^{n-1/2} - dt curl E^n, then E^{n+1} = E^n + dt (curl B^{n+1/2} - J -
+// J_ion), then first-order Mur on the tangential E at open z ends.  The
+// current is double-buffered: the step deposits into J[fbuf], the E pass reads
+// it and clears J[fbuf^1], into which the next step deposits.  This is the
+// standard leapfrog, algebraically equal to two half steps of B around the E
+// step with E and B both at integer time.
 #include <hip/hip_runtime.h>
 
 #include "launch.hpp"
@@ -431,38 +429,61 @@ __global__ __launch_bounds__(BLOCK) void k_particles(const BatchTable* __restric
     R* const* Bg = reinterpret_cast<R* const*>(rd.B[fb]);
     const R dt = R(rd.dt);
 
-    // ---- stage E^n and B^{n-1/2} of the window; clear the current window
+    // ---- stage E^n and B^{n-1/2} of the window; clear the current window.
+    // Every thread issues all of its window loads before the first LDS
+    // write, so a tile pays one memory latency instead of one per row.
     __syncthreads();
     const int nwin = Wd[0] * Wd[1] * Wd[2];
-    for (int q = threadIdx.x; q < nwin; q += BLOCK) {
-      const int rz = q % Wd[0];
-      const int t = q / Wd[0];
-      const int rx = t % Wd[1], ry = t / Wd[1];
-      const int s = (ry * WXM + rx) * WZM + rz;
-      const int gk = w0[0] + rz;
-      const int gi = wrap2(w0[1] + rx, nx);
-      const int gj = DIM == 3 ? wrap2(w0[2] + ry, ny) : 0;
-      bool zn = true, zh = true;
-      int kk = gk;
-      if (open) {
-        zn = gk >= 0 && gk <= nz;
-        zh = gk >= 0 && gk < nz;
-        kk = min(max(gk, 0), nzf - 1);
-      } else {
-        kk = wrap2(gk, nz);
+    {
+      constexpr int NU = (WV + BLOCK - 1) / BLOCK;
+      R ld[NU][6];
+      int sidx[NU];
+      bool znv[NU], zhv[NU];
+#pragma unroll
+      for (int u = 0; u < NU; ++u) {
+        const int q = threadIdx.x + u * BLOCK;
+        sidx[u] = -1;
+        if (q < nwin) {
+          const int rz = q % Wd[0];
+          const int t = q / Wd[0];
+          const int rx = t % Wd[1], ry = t / Wd[1];
+          sidx[u] = (ry * WXM + rx) * WZM + rz;
+          const int gk = w0[0] + rz;
+          const int gi = wrap2(w0[1] + rx, nx);
+          const int gj = DIM == 3 ? wrap2(w0[2] + ry, ny) : 0;
+          int kk;
+          if (open) {
+            znv[u] = gk >= 0 && gk <= nz;
+            zhv[u] = gk >= 0 && gk < nz;
+            kk = min(max(gk, 0), nzf - 1);
+          } else {
+            znv[u] = zhv[u] = true;
+            kk = wrap2(gk, nz);
+          }
+          const long long g = ((long long)gj * nx + gi) * nzf + kk;
+          ld[u][0] = Eg[0][g];
+          ld[u][1] = Eg[1][g];
+          ld[u][2] = Eg[2][g];
+          ld[u][3] = Bg[0][g];
+          ld[u][4] = Bg[1][g];
+          ld[u][5] = Bg[2][g];
+        }
       }
-      const long long g = ((long long)gj * nx + gi) * nzf + kk;
-      const R ex = Eg[0][g], ey = Eg[1][g], ez = Eg[2][g];
-      const R bx = Bg[0][g], by = Bg[1][g], bz = Bg[2][g];
-      sF[0][s] = zn ? ex : R(0);
-      sF[1][s] = zn ? ey : R(0);
-      sF[2][s] = zh ? ez : R(0);
-      sF[3][s] = zh ? bx : R(0);
-      sF[4][s] = zh ? by : R(0);
-      sF[5][s] = zn ? bz : R(0);
-      sJ[0][s] = 0;
-      sJ[1][s] = 0;
-      sJ[2][s] = 0;
+#pragma unroll
+      for (int u = 0; u < NU; ++u) {
+        const int s = sidx[u];
+        if (s >= 0) {
+          sF[0][s] = znv[u] ? ld[u][0] : R(0);
+          sF[1][s] = znv[u] ? ld[u][1] : R(0);
+          sF[2][s] = zhv[u] ? ld[u][2] : R(0);
+          sF[3][s] = zhv[u] ? ld[u][3] : R(0);
+          sF[4][s] = zhv[u] ? ld[u][4] : R(0);
+          sF[5][s] = znv[u] ? ld[u][5] : R(0);
+          sJ[0][s] = 0;
+          sJ[1][s] = 0;
+          sJ[2][s] = 0;
+        }
+      }
     }
     __syncthreads();
     // ---- B^n = B^{n-1/2} - dt/2 curl E^n on the window (last layer unused)
@@ -507,8 +528,53 @@ __global__ __launch_bounds__(BLOCK) void k_particles(const BatchTable* __restric
     int bmax0 = -(1 << 20), bmax1 = -(1 << 20), bmax2 = -(1 << 20);
     bool bad = false;
 
-    for (long long p = p0 + threadIdx.x; p < p1; p += BLOCK) {
-      const int c = cellp[p];
+    // software pipeline: the state of the particles two iterations ahead is
+    // loaded while the current one is advanced (occupancy is set by the LDS
+    // window, so the extra registers are free)
+    long long p = p0 + threadIdx.x;
+    int cA = -1, cB = -1;
+    R oA0 = R(0), oA1 = R(0), oA2 = R(0), uA0 = R(0), uA1 = R(0), uA2 = R(0);
+    R oB0 = R(0), oB1 = R(0), oB2 = R(0), uB0 = R(0), uB1 = R(0), uB2 = R(0);
+    if (p < p1) {
+      cA = cellp[p];
+      oA0 = o0p[p];
+      oA1 = o1p[p];
+      if (DIM == 3) oA2 = o2p[p];
+      uA0 = uxp[p];
+      uA1 = uyp[p];
+      uA2 = uzp[p];
+    }
+    if (p + BLOCK < p1) {
+      const long long q = p + BLOCK;
+      cB = cellp[q];
+      oB0 = o0p[q];
+      oB1 = o1p[q];
+      if (DIM == 3) oB2 = o2p[q];
+      uB0 = uxp[q];
+      uB1 = uyp[q];
+      uB2 = uzp[q];
+    }
+    for (; p < p1; p += BLOCK) {
+      const int c = cA;
+      R o[3] = {oA0, oA1, oA2};
+      R ux = uA0, uy = uA1, uz = uA2;
+      cA = cB;
+      oA0 = oB0;
+      oA1 = oB1;
+      oA2 = oB2;
+      uA0 = uB0;
+      uA1 = uB1;
+      uA2 = uB2;
+      const long long pn = p + 2 * BLOCK;
+      if (pn < p1) {
+        cB = cellp[pn];
+        oB0 = o0p[pn];
+        oB1 = o1p[pn];
+        if (DIM == 3) oB2 = o2p[pn];
+        uB0 = uxp[pn];
+        uB1 = uyp[pn];
+        uB2 = uzp[pn];
+      }
       if (c < 0) continue;  // removed
       const int k = cell_k(c), i = cell_i(c), j = DIM == 3 ? cell_j(c) : 0;
       const int rk = open ? k - t0[0] : relw(k, t0[0], nz, gz);
@@ -522,11 +588,6 @@ __global__ __launch_bounds__(BLOCK) void k_particles(const BatchTable* __restric
         if (e < (unsigned long long)rd.capacity) rd.slowq[e] = (int)p;
         continue;
       }
-      R o[3];
-      o[0] = o0p[p];
-      o[1] = o1p[p];
-      o[2] = DIM == 3 ? o2p[p] : R(0);
-      R ux = uxp[p], uy = uyp[p], uz = uzp[p];
       const int base = (wj * WXM + wi) * WZM + wk;
       int cr[3];
       bad |= advance<DIM, R, PUSHER>(
@@ -686,98 +747,126 @@ __global__ __launch_bounds__(256) void k_particles_hbm(const BatchTable* __restr
 }
 
 // ------------------------------------------------------------------ fields
+// Three passes, one thread per grid point each, so that every thread issues
+// only a handful of coalesced loads:
+//   k_bhalf: B^{n+1/2} = B^{n-1/2} - dt curl E^n           (B[fb] -> B[fb^1])
+//   k_efull: E^{n+1} = E^n + dt (curl B^{n+1/2} - J - J_ion) (E[fb] -> E[fb^1]),
+//            and clears the current buffer of the next step (J[fb^1])
+//   k_mur:   first-order Mur on the tangential E at the open z ends, from
+//            E^n (still in E[fb]) and the interior E^{n+1}.
 template <int DIM, typename R>
-__global__ __launch_bounds__(256) void k_fields(const BatchTable* __restrict__ bt) {
+struct FieldView {
+  int nzf, nx, ny, nz;
+  bool open;
+  __device__ __forceinline__ int wx(int i) const { return i < 0 ? i + nx : (i >= nx ? i - nx : i); }
+  __device__ __forceinline__ int wy(int j) const {
+    return DIM == 3 ? (j < 0 ? j + ny : (j >= ny ? j - ny : j)) : 0;
+  }
+  // z index of component c, or -1 outside the open range
+  __device__ __forceinline__ int zk(int c, int k) const {
+    if (open) return (k >= 0 && k < (stag(c, 0) ? nz : nz + 1)) ? k : -1;
+    return k < 0 ? k + nz : (k >= nz ? k - nz : k);
+  }
+  __device__ __forceinline__ R at(R* const* F, int c, int fc, int k, int i, int j) const {
+    const int z = zk(fc, k);
+    if (z < 0) return R(0);
+    return F[c][((long long)wy(j) * nx + wx(i)) * nzf + z];
+  }
+};
+
+template <int DIM, typename R>
+__global__ __launch_bounds__(256) void k_bhalf(const BatchTable* __restrict__ bt) {
   const XcdSplit xs(bt->cellblk);
   for (long long w = xs.beg; w < xs.end; w += xs.stride) {
     const int r = __builtin_amdgcn_readfirstlane(locate(bt->pre_cellblk, bt->n, w));
     const RunDev& rd = *bt->run[r];
     const long long q = (w - bt->pre_cellblk[r]) * CELL_BLOCK + threadIdx.x;
     if (q >= rd.npts) continue;
-    const int nzf = rd.nzf, nx = rd.nx, ny = rd.ny, nz = rd.nz;
-    const int k = (int)(q % nzf);
-    const long long t = q / nzf;
-    const int i = (int)(t % nx), j = (int)(t / nx);
+    const FieldView<DIM, R> V{rd.nzf, rd.nx, rd.ny, rd.nz, rd.open != 0};
+    const int k = (int)(q % V.nzf);
+    const long long t = q / V.nzf;
+    const int i = (int)(t % V.nx), j = (int)(t / V.nx);
     const int fb = rd.ctr->fbuf;
-    const bool open = rd.open != 0;
     R* const* E = reinterpret_cast<R* const*>(rd.E[fb]);
     R* const* Bm = reinterpret_cast<R* const*>(rd.B[fb]);
-    R* const* En = reinterpret_cast<R* const*>(rd.E[fb ^ 1]);
-    R* const* Bn = reinterpret_cast<R* const*>(rd.B[fb ^ 1]);
-    const long long* const* J = reinterpret_cast<const long long* const*>(rd.J[fb]);
-    long long* const* Jnext = reinterpret_cast<long long* const*>(rd.J[fb ^ 1]);
-    const double jinv = rd.jinv;
+    R* const* Bh = reinterpret_cast<R* const*>(rd.B[fb ^ 1]);
     const R dt = R(rd.dt);
     const R idz = R(1.0 / rd.dz), idx = R(1.0 / rd.dx), idy = DIM == 3 ? R(1.0 / rd.dy) : R(0);
-
-    auto wx = [&](int ii) { return ii < 0 ? ii + nx : (ii >= nx ? ii - nx : ii); };
-    auto wy = [&](int jj) { return DIM == 3 ? (jj < 0 ? jj + ny : (jj >= ny ? jj - ny : jj)) : 0; };
-    // z index of component c, or -1 if outside the open range
-    auto zk = [&](int c, int kk) {
-      if (open) return (kk >= 0 && kk < (stag(c, 0) ? nz : nz + 1)) ? kk : -1;
-      return kk < 0 ? kk + nz : (kk >= nz ? kk - nz : kk);
-    };
-    auto Ev = [&](int c, int kk, int ii, int jj) -> R {
-      const int z = zk(c, kk);
-      if (z < 0) return R(0);
-      return E[c][((long long)wy(jj) * nx + wx(ii)) * nzf + z];
-    };
-    // B^{n+1/2} = B^{n-1/2} - dt curl E^n at (kk, ii, jj)
-    auto Bh = [&](int c, int kk, int ii, int jj) -> R {
-      const int z = zk(3 + c, kk);
-      if (z < 0) return R(0);
-      R curl;
-      if (c == 0)
-        curl = (DIM == 3 ? (Ev(2, kk, ii, jj + 1) - Ev(2, kk, ii, jj)) * idy : R(0)) -
-               (Ev(1, kk + 1, ii, jj) - Ev(1, kk, ii, jj)) * idz;
-      else if (c == 1)
-        curl = (Ev(0, kk + 1, ii, jj) - Ev(0, kk, ii, jj)) * idz -
-               (Ev(2, kk, ii + 1, jj) - Ev(2, kk, ii, jj)) * idx;
-      else
-        curl = (Ev(1, kk, ii + 1, jj) - Ev(1, kk, ii, jj)) * idx -
-               (DIM == 3 ? (Ev(0, kk, ii, jj + 1) - Ev(0, kk, ii, jj)) * idy : R(0));
-      return Bm[c][((long long)wy(jj) * nx + wx(ii)) * nzf + z] - dt * curl;
-    };
-    const R jion = R(rd.jion_z);
-    const long long g0 = ((long long)j * nx + i) * nzf;
-    auto Jv = [&](int c, int kk) -> R {
-      const int z = zk(c, kk);
-      return z < 0 ? R(0) : R((double)J[c][g0 + z] * jinv);
-    };
-    // E^{n+1} at (kk, i, j) from Ampere's law
-    auto Enew = [&](int c, int kk) -> R {
-      if (c == 0)
-        return Ev(0, kk, i, j) +
-               dt * ((DIM == 3 ? (Bh(2, kk, i, j) - Bh(2, kk, i, j - 1)) * idy : R(0)) -
-                     (Bh(1, kk, i, j) - Bh(1, kk - 1, i, j)) * idz - Jv(0, kk));
-      if (c == 1)
-        return Ev(1, kk, i, j) + dt * ((Bh(0, kk, i, j) - Bh(0, kk - 1, i, j)) * idz -
-                                       (Bh(2, kk, i, j) - Bh(2, kk, i - 1, j)) * idx - Jv(1, kk));
-      return Ev(2, kk, i, j) +
-             dt * ((Bh(1, kk, i, j) - Bh(1, kk, i - 1, j)) * idx -
-                   (DIM == 3 ? (Bh(0, kk, i, j) - Bh(0, kk, i, j - 1)) * idy : R(0)) - Jv(2, kk) - jion);
-    };
-    const long long g = g0 + k;
-    const R cm = R((rd.dt - rd.dz) / (rd.dt + rd.dz));
-#pragma unroll
-    for (int c = 0; c < 2; ++c) {  // tangential E (node-centred in z)
-      R v;
-      if (open && k == 0)
-        v = Ev(c, 1, i, j) + cm * (Enew(c, 1) - Ev(c, 0, i, j));
-      else if (open && k == nz)
-        v = Ev(c, nz - 1, i, j) + cm * (Enew(c, nz - 1) - Ev(c, nz, i, j));
-      else
-        v = Enew(c, k);
-      En[c][g] = v;
+    const R ex = V.at(E, 0, 0, k, i, j), ey = V.at(E, 1, 1, k, i, j), ez = V.at(E, 2, 2, k, i, j);
+    const R ey_z = V.at(E, 1, 1, k + 1, i, j), ex_z = V.at(E, 0, 0, k + 1, i, j);
+    const R ez_x = V.at(E, 2, 2, k, i + 1, j), ey_x = V.at(E, 1, 1, k, i + 1, j);
+    R ez_y = R(0), ex_y = R(0);
+    if (DIM == 3) {
+      ez_y = V.at(E, 2, 2, k, i, j + 1);
+      ex_y = V.at(E, 0, 0, k, i, j + 1);
     }
-    En[2][g] = (zk(2, k) >= 0) ? Enew(2, k) : R(0);
-#pragma unroll
-    for (int c = 0; c < 3; ++c) Bn[c][g] = Bh(c, k, i, j);
-    // the current read above (own point and, at the Mur ends, the next
-    // interior point) stays intact; the buffer of the next step is cleared
-    Jnext[0][g] = 0;
-    Jnext[1][g] = 0;
-    Jnext[2][g] = 0;
+    const R cx = (ez_y - ez) * idy - (ey_z - ey) * idz;
+    const R cy = (ex_z - ex) * idz - (ez_x - ez) * idx;
+    const R cz = (ey_x - ey) * idx - (ex_y - ex) * idy;
+    Bh[0][q] = V.zk(3, k) >= 0 ? Bm[0][q] - dt * cx : R(0);
+    Bh[1][q] = V.zk(4, k) >= 0 ? Bm[1][q] - dt * cy : R(0);
+    Bh[2][q] = V.zk(5, k) >= 0 ? Bm[2][q] - dt * cz : R(0);
+  }
+}
+
+template <int DIM, typename R>
+__global__ __launch_bounds__(256) void k_efull(const BatchTable* __restrict__ bt) {
+  const XcdSplit xs(bt->cellblk);
+  for (long long w = xs.beg; w < xs.end; w += xs.stride) {
+    const int r = __builtin_amdgcn_readfirstlane(locate(bt->pre_cellblk, bt->n, w));
+    const RunDev& rd = *bt->run[r];
+    const long long q = (w - bt->pre_cellblk[r]) * CELL_BLOCK + threadIdx.x;
+    if (q >= rd.npts) continue;
+    const FieldView<DIM, R> V{rd.nzf, rd.nx, rd.ny, rd.nz, rd.open != 0};
+    const int k = (int)(q % V.nzf);
+    const long long t = q / V.nzf;
+    const int i = (int)(t % V.nx), j = (int)(t / V.nx);
+    const int fb = rd.ctr->fbuf;
+    R* const* E = reinterpret_cast<R* const*>(rd.E[fb]);
+    R* const* En = reinterpret_cast<R* const*>(rd.E[fb ^ 1]);
+    R* const* Bh = reinterpret_cast<R* const*>(rd.B[fb ^ 1]);
+    const long long* const* J = reinterpret_cast<const long long* const*>(rd.J[fb]);
+    long long* const* Jnext = reinterpret_cast<long long* const*>(rd.J[fb ^ 1]);
+    const R dt = R(rd.dt);
+    const R idz = R(1.0 / rd.dz), idx = R(1.0 / rd.dx), idy = DIM == 3 ? R(1.0 / rd.dy) : R(0);
+    const double jinv = rd.jinv;
+    const R bx = V.at(Bh, 0, 3, k, i, j), by = V.at(Bh, 1, 4, k, i, j), bz = V.at(Bh, 2, 5, k, i, j);
+    const R by_z = V.at(Bh, 1, 4, k - 1, i, j), bx_z = V.at(Bh, 0, 3, k - 1, i, j);
+    const R bz_x = V.at(Bh, 2, 5, k, i - 1, j), by_x = V.at(Bh, 1, 4, k, i - 1, j);
+    R bz_y = R(0), bx_y = R(0);
+    if (DIM == 3) {
+      bz_y = V.at(Bh, 2, 5, k, i, j - 1);
+      bx_y = V.at(Bh, 0, 3, k, i, j - 1);
+    }
+    const R jx = R((double)J[0][q] * jinv), jy = R((double)J[1][q] * jinv), jz = R((double)J[2][q] * jinv);
+    const bool zn = V.zk(0, k) >= 0, zh = V.zk(2, k) >= 0;
+    En[0][q] = zn ? E[0][q] + dt * ((bz - bz_y) * idy - (by - by_z) * idz - jx) : R(0);
+    En[1][q] = zn ? E[1][q] + dt * ((bx - bx_z) * idz - (bz - bz_x) * idx - jy) : R(0);
+    En[2][q] = zh ? E[2][q] + dt * ((by - by_x) * idx - (bx - bx_y) * idy - jz - R(rd.jion_z)) : R(0);
+    Jnext[0][q] = 0;
+    Jnext[1][q] = 0;
+    Jnext[2][q] = 0;
+  }
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_mur(const BatchTable* __restrict__ bt) {
+  const XcdSplit xs(bt->cellblk);
+  for (long long w = xs.beg; w < xs.end; w += xs.stride) {
+    const int r = __builtin_amdgcn_readfirstlane(locate(bt->pre_cellblk, bt->n, w));
+    const RunDev& rd = *bt->run[r];
+    if (!rd.open) continue;
+    const long long q = (w - bt->pre_cellblk[r]) * CELL_BLOCK + threadIdx.x;
+    if (q >= 2 * rd.nperp) continue;
+    const int side = (int)(q / rd.nperp);
+    const long long col = (q % rd.nperp) * rd.nzf;
+    const int fb = rd.ctr->fbuf;
+    R* const* E = reinterpret_cast<R* const*>(rd.E[fb]);
+    R* const* En = reinterpret_cast<R* const*>(rd.E[fb ^ 1]);
+    const R cm = R((rd.dt - rd.dz) / (rd.dt + rd.dz));
+    const int kb = side ? rd.nz : 0, ki = side ? rd.nz - 1 : 1;
+    for (int c = 0; c < 2; ++c)
+      En[c][col + kb] = E[c][col + ki] + cm * (En[c][col + ki] - E[c][col + kb]);
   }
 }
 
@@ -794,9 +883,13 @@ __global__ void k_advance(const BatchTable* __restrict__ bt) {
 }
 
 // ------------------------------------------------------------------ launch
+// workgroup size of the particle kernel (3D split-precision path)
+#ifndef PIC_PBLOCK3
+#define PIC_PBLOCK3 256
+#endif
 template <int DIM, typename R>
 struct PBlock {
-  static constexpr int value = 256;
+  static constexpr int value = (DIM == 3 && sizeof(R) == 4) ? PIC_PBLOCK3 : 256;
 };
 
 int grid_particles(int dims, int prec, int ncu) {
@@ -835,13 +928,18 @@ void launch_particles(int dims, int prec, int pusher, const BatchTable* bt, int 
   }
 }
 
+template <int DIM, typename R>
+static void lf(const BatchTable* bt, int grid, hipStream_t s) {
+  hipLaunchKernelGGL((k_bhalf<DIM, R>), dim3(grid), dim3(256), 0, s, bt);
+  hipLaunchKernelGGL((k_efull<DIM, R>), dim3(grid), dim3(256), 0, s, bt);
+  hipLaunchKernelGGL((k_mur<R>), dim3(grid), dim3(256), 0, s, bt);
+}
+
 void launch_fields(int dims, int prec, const BatchTable* bt, int grid, hipStream_t s) {
   if (dims == 3) {
-    if (prec) hipLaunchKernelGGL((k_fields<3, double>), dim3(grid), dim3(256), 0, s, bt);
-    else hipLaunchKernelGGL((k_fields<3, float>), dim3(grid), dim3(256), 0, s, bt);
+    if (prec) lf<3, double>(bt, grid, s); else lf<3, float>(bt, grid, s);
   } else {
-    if (prec) hipLaunchKernelGGL((k_fields<2, double>), dim3(grid), dim3(256), 0, s, bt);
-    else hipLaunchKernelGGL((k_fields<2, float>), dim3(grid), dim3(256), 0, s, bt);
+    if (prec) lf<2, double>(bt, grid, s); else lf<2, float>(bt, grid, s);
   }
 }
 

@@ -15,6 +15,12 @@
 
 namespace pic {
 
+// u'^2 above which the gamma solve runs in FP64 (gamma ~ 100)
+#ifndef PIC_GAMMA2_FP64
+#define PIC_GAMMA2_FP64 1.0e4
+#endif
+constexpr double GAMMA2_FP64 = PIC_GAMMA2_FP64;
+
 template <typename R>
 __device__ __forceinline__ void push_vay(R& ux, R& uy, R& uz, R ex, R ey, R ez, R bx, R by, R bz,
                                          R eps) {
@@ -28,15 +34,36 @@ __device__ __forceinline__ void push_vay(R& ux, R& uy, R& uz, R ex, R ey, R ez, 
   const R upz = uz + eps * (R(2) * ez + (vx * by - vy * bx));
   const R tx = eps * bx, ty = eps * by, tz = eps * bz;
   // gamma_new^2 = (sigma + sqrt(sigma^2 + 4 (tau^2 + u*^2))) / 2,
-  // sigma = 1 + u'^2 - tau^2, u* = u'.tau   (FP64)
-  const double dux = upx, duy = upy, duz = upz, dtx = tx, dty = ty, dtz = tz;
-  const double ustar = dux * dtx + duy * dty + duz * dtz;
-  const double tau2 = dtx * dtx + dty * dty + dtz * dtz;
-  const double sigma = 1.0 + (dux * dux + duy * duy + duz * duz) - tau2;
-  const double a4 = 4.0 * (tau2 + ustar * ustar);
-  const double disc = sqrt(sigma * sigma + a4);
-  const double g2 = sigma >= 0.0 ? 0.5 * (sigma + disc) : 0.5 * a4 / (disc - sigma);
-  const R ign = R(1.0 / sqrt(g2));
+  // sigma = 1 + u'^2 - tau^2, u* = u'.tau.  At large gamma the "1 +" and the
+  // tau^2 terms of sigma drop below FP32 resolution, so the solve runs in FP64
+  // whenever some lane of the wavefront has u'^2 > GAMMA2_FP64 (gamma above
+  // ~100); below that FP32 keeps gamma_new to ~1e-8 relative.  The switch is
+  // wavefront-uniform, so no lane pays for both.
+  R ign;
+  const R up2 = upx * upx + upy * upy + upz * upz;
+  if (sizeof(R) == 8 || __any(up2 > R(GAMMA2_FP64))) {
+    const double dux = upx, duy = upy, duz = upz, dtx = tx, dty = ty, dtz = tz;
+    const double ustar = dux * dtx + duy * dty + duz * dtz;
+    const double tau2 = dtx * dtx + dty * dty + dtz * dtz;
+    const double sigma = 1.0 + (dux * dux + duy * duy + duz * duz) - tau2;
+    const double a4 = 4.0 * (tau2 + ustar * ustar);
+    const double disc = sqrt(sigma * sigma + a4);
+    const double g2 = sigma >= 0.0 ? 0.5 * (sigma + disc) : 0.5 * a4 / (disc - sigma);
+    // gamma_new^2 carries the FP64 accuracy; its reciprocal square root is
+    // taken in R (for FP32 one v_rsq_f32, relative error ~1e-7)
+    if constexpr (sizeof(R) == 4)
+      ign = rsqrtf((float)g2);
+    else
+      ign = R(1.0 / sqrt(g2));
+  } else {
+    const R ustar = upx * tx + upy * ty + upz * tz;
+    const R tau2 = tx * tx + ty * ty + tz * tz;
+    const R sigma = R(1) + up2 - tau2;
+    const R a4 = R(4) * (tau2 + ustar * ustar);
+    const R disc = sqrt(sigma * sigma + a4);
+    const R g2 = sigma >= R(0) ? R(0.5) * (sigma + disc) : R(0.5) * a4 / (disc - sigma);
+    ign = rsqrtf(g2);
+  }
   // u_new = s (u' + (u'.t) t + u' x t),  t = tau / gamma_new,  s = 1/(1+t^2),
   // evaluated as u' + s ((u'.t) t + u' x t - t^2 u'): the small rotation is
   // formed on its own and added once, so the large components of u' are
