@@ -12,6 +12,9 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libpic.so")
 OBJ = os.path.join(HERE, "_build")
 SOURCES = ["k_step.hip", "k_sort.hip", "k_aux.hip", "k_push_bench.hip", "pic_api.hip"]
+# the C ABI holds host code only: no device pass (the device pass types the
+# run descriptor's pointers with the global and constant address spaces)
+HOST_ONLY = {"pic_api.hip"}
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-munsafe-fp-atomics",
     # no packed FP32 instructions (v_pk_*_f32) anywhere in the device code
@@ -22,7 +25,8 @@ FLAGS = [
 
 def _compile(src: str) -> str:
     obj = os.path.join(OBJ, src + ".o")
-    cmd = ["hipcc", *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    extra = ["--cuda-host-only"] if src in HOST_ONLY else []
+    cmd = ["hipcc", *FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")

@@ -20,7 +20,7 @@ namespace pic {
 // ------------------------------------------------------------------ laser
 template <typename R>
 __global__ void k_laser(const RunDev* __restrict__ rdp) {
-  const RunDev& rd = *rdp;
+  RunC& rd = *(RunC*)rdp;
   const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= rd.npts) return;
   const int k = (int)(q % rd.nzf);
@@ -71,7 +71,7 @@ __global__ void k_laser(const RunDev* __restrict__ rdp) {
 
 // E value at integer index with the open/periodic z rules
 template <typename R>
-__device__ __forceinline__ double ev(const RunDev& rd, R* const* E, int c, int k, int i, int j) {
+__device__ __forceinline__ double ev(RunC& rd, R* const* E, int c, int k, int i, int j) {
   i = wrapi(i, rd.nx);
   j = rd.dims == 3 ? wrapi(j, rd.ny) : 0;
   if (rd.open) {
@@ -84,7 +84,7 @@ __device__ __forceinline__ double ev(const RunDev& rd, R* const* E, int c, int k
 
 // curl of E at the B point of component c (0,1,2 = x,y,z)
 template <typename R>
-__device__ __forceinline__ double curl_e(const RunDev& rd, R* const* E, int c, int k, int i, int j) {
+__device__ __forceinline__ double curl_e(RunC& rd, R* const* E, int c, int k, int i, int j) {
   const double idz = 1.0 / rd.dz, idx = 1.0 / rd.dx, idy = rd.dims == 3 ? 1.0 / rd.dy : 0.0;
   if (c == 0)
     return (ev(rd, E, 2, k, i, j + 1) - ev(rd, E, 2, k, i, j)) * idy -
@@ -99,7 +99,7 @@ __device__ __forceinline__ double curl_e(const RunDev& rd, R* const* E, int c, i
 // B^{n+s dt} from B at the stored time: out = B + coef * curl E (valid points)
 template <typename R>
 __global__ void k_bshift(const RunDev* __restrict__ rdp, int src, int dst, double coef) {
-  const RunDev& rd = *rdp;
+  RunC& rd = *(RunC*)rdp;
   const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= rd.npts) return;
   const int k = (int)(q % rd.nzf);
@@ -158,7 +158,7 @@ __device__ double block_max(double v, double* sh) {
   return r;
 }
 
-__device__ __forceinline__ bool interior(const RunDev& rd, int comp, int k) {
+__device__ __forceinline__ bool interior(RunC& rd, int comp, int k) {
   if (!rd.open) return true;
   const int hi = stag(comp, 0) ? rd.nz - 3 : rd.nz - 2;
   return k >= 2 && k <= hi;
@@ -177,8 +177,8 @@ __global__ void k_fill(double* p, long long n, double v) {
 // position.
 template <int DIM, typename R>
 __global__ void k_rho(const RunDev* __restrict__ rdp, double* rho, int use_snap) {
-  const RunDev& rd = *rdp;
-  const Counters& c = *rd.ctr;
+  RunC& rd = *(RunC*)rdp;
+  const PIC_G Counters& c = *rd.ctr;
   const int pb = c.pbuf;
   const double qw = -rd.weight;
   double dv = rd.dz * rd.dx * (DIM == 3 ? rd.dy : 1.0);
@@ -205,14 +205,14 @@ __global__ void k_rho(const RunDev* __restrict__ rdp, double* rho, int use_snap)
             kk = wrapi(kk, rd.nz);
           }
           const double wgt = wz[cz] * wx[cx] * (DIM == 3 ? wy[cy] : 1.0);
-          atomicAdd(rho + gidx(rd, kk, ii, jj), s * wgt);
+          g_add((PIC_G double*)rho + gidx(rd, kk, ii, jj), s * wgt);
         }
   }
 }
 
 __global__ void k_snap(const RunDev* __restrict__ rdp) {
-  const RunDev& rd = *rdp;
-  const Counters& c = *rd.ctr;
+  RunC& rd = *(RunC*)rdp;
+  const PIC_G Counters& c = *rd.ctr;
   for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < c.n_slots;
        q += (long long)gridDim.x * blockDim.x)
     rd.cell_snap[q] = rd.cell[c.pbuf][q];
@@ -220,7 +220,7 @@ __global__ void k_snap(const RunDev* __restrict__ rdp) {
 
 // divergence at node (k,i,j) of a field staggered like E
 template <typename R>
-__device__ __forceinline__ double div_e(const RunDev& rd, R* const* F, int k, int i, int j) {
+__device__ __forceinline__ double div_e(RunC& rd, R* const* F, int k, int i, int j) {
   const double idz = 1.0 / rd.dz, idx = 1.0 / rd.dx, idy = rd.dims == 3 ? 1.0 / rd.dy : 0.0;
   return (ev(rd, F, 0, k, i, j) - ev(rd, F, 0, k, i - 1, j)) * idx +
          (ev(rd, F, 1, k, i, j) - ev(rd, F, 1, k, i, j - 1)) * idy +
@@ -228,7 +228,7 @@ __device__ __forceinline__ double div_e(const RunDev& rd, R* const* F, int k, in
 }
 
 // divergence of the fixed-point current at node (k,i,j), in units of 1/jscale
-__device__ __forceinline__ double jv(const RunDev& rd, const long long* const* J, int c, int k, int i, int j) {
+__device__ __forceinline__ double jv(RunC& rd, const long long* const* J, int c, int k, int i, int j) {
   i = wrapi(i, rd.nx);
   j = rd.dims == 3 ? wrapi(j, rd.ny) : 0;
   if (rd.open) {
@@ -238,7 +238,7 @@ __device__ __forceinline__ double jv(const RunDev& rd, const long long* const* J
   }
   return (double)J[c][gidx(rd, k, i, j)];
 }
-__device__ __forceinline__ double div_j(const RunDev& rd, const long long* const* J, int k, int i, int j) {
+__device__ __forceinline__ double div_j(RunC& rd, const long long* const* J, int k, int i, int j) {
   const double idz = 1.0 / rd.dz, idx = 1.0 / rd.dx, idy = rd.dims == 3 ? 1.0 / rd.dy : 0.0;
   return (jv(rd, J, 0, k, i, j) - jv(rd, J, 0, k, i - 1, j)) * idx +
          (jv(rd, J, 1, k, i, j) - jv(rd, J, 1, k, i, j - 1)) * idy +
@@ -249,7 +249,7 @@ __device__ __forceinline__ double div_j(const RunDev& rd, const long long* const
 template <typename R>
 __global__ __launch_bounds__(256) void k_cont(const RunDev* __restrict__ rdp) {
   __shared__ double sh[4];
-  const RunDev& rd = *rdp;
+  RunC& rd = *(RunC*)rdp;
   const long long* const* J = reinterpret_cast<const long long* const*>(rd.J[rd.ctr->fbuf]);
   double res = 0.0, rmax = 0.0;
   for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < rd.npts;
@@ -272,7 +272,7 @@ __global__ __launch_bounds__(256) void k_cont(const RunDev* __restrict__ rdp) {
 }
 
 __global__ void k_cont_fin(const RunDev* __restrict__ rdp) {
-  Counters* c = rdp->ctr;
+  PIC_G Counters* c = rdp->ctr;
   const double res = __longlong_as_double((long long)c->cont_res_bits);
   const double rho = __longlong_as_double((long long)c->cont_rho_bits);
   const double rel = rho > 0 ? res / rho : res;
@@ -283,7 +283,7 @@ __global__ void k_cont_fin(const RunDev* __restrict__ rdp) {
 
 template <typename R>
 __global__ void k_jlast(const RunDev* __restrict__ rdp) {
-  const RunDev& rd = *rdp;
+  RunC& rd = *(RunC*)rdp;
   for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < rd.npts;
        q += (long long)gridDim.x * blockDim.x)
     for (int c = 0; c < 3; ++c)
@@ -296,7 +296,7 @@ __global__ void k_jlast(const RunDev* __restrict__ rdp) {
 template <typename R>
 __global__ __launch_bounds__(256) void k_gauss(const RunDev* __restrict__ rdp, int mode) {
   __shared__ double sh[4];
-  const RunDev& rd = *rdp;
+  RunC& rd = *(RunC*)rdp;
   R* const* E = reinterpret_cast<R* const*>(rd.E[rd.ctr->fbuf]);
   double m = 0.0;
   for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < rd.npts;
@@ -316,7 +316,7 @@ __global__ __launch_bounds__(256) void k_gauss(const RunDev* __restrict__ rdp, i
   m = block_max(m, sh);
   if (threadIdx.x == 0) {
     if (mode == 0)
-      atomic_max_pos(reinterpret_cast<unsigned long long*>(&rd.ctr->rho0_max), m);
+      atomic_max_pos((PIC_G unsigned long long*)&rd.ctr->rho0_max, m);
     else
       atomic_max_pos(&rd.ctr->amax[1], m);
   }
@@ -326,7 +326,7 @@ __global__ __launch_bounds__(256) void k_gauss(const RunDev* __restrict__ rdp, i
 template <typename R>
 __global__ __launch_bounds__(256) void k_diag_fields(const RunDev* __restrict__ rdp) {
   __shared__ double sh[4];
-  const RunDev& rd = *rdp;
+  RunC& rd = *(RunC*)rdp;
   const int fb = rd.ctr->fbuf;
   R* const* E = reinterpret_cast<R* const*>(rd.E[fb]);
   double ue = 0.0, ub = 0.0, ezm = 0.0;
@@ -354,8 +354,8 @@ __global__ __launch_bounds__(256) void k_diag_fields(const RunDev* __restrict__ 
   ezm = block_max(ezm, sh);
   if (threadIdx.x == 0) {
     const double dv = rd.dz * rd.dx * (rd.dims == 3 ? rd.dy : 1.0);
-    atomicAdd(&rd.ctr->acc[0], 0.5 * ue * dv);
-    atomicAdd(&rd.ctr->acc[1], 0.5 * ub * dv);
+    g_add(&rd.ctr->acc[0], 0.5 * ue * dv);
+    g_add(&rd.ctr->acc[1], 0.5 * ub * dv);
     atomic_max_pos(&rd.ctr->amax[0], ezm);
   }
 }
@@ -363,8 +363,8 @@ __global__ __launch_bounds__(256) void k_diag_fields(const RunDev* __restrict__ 
 template <int DIM, typename R>
 __global__ __launch_bounds__(256) void k_diag_particles(const RunDev* __restrict__ rdp) {
   __shared__ double sh[4];
-  const RunDev& rd = *rdp;
-  const Counters& c = *rd.ctr;
+  RunC& rd = *(RunC*)rdp;
+  const PIC_G Counters& c = *rd.ctr;
   const int pb = c.pbuf;
   double ke = 0.0, cnt = 0.0;
   for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < c.n_slots;
@@ -385,8 +385,8 @@ __global__ __launch_bounds__(256) void k_diag_particles(const RunDev* __restrict
   ke = block_sum(ke, sh);
   cnt = block_sum(cnt, sh);
   if (threadIdx.x == 0) {
-    atomicAdd(&rd.ctr->acc[2], ke);
-    atomicAdd(&rd.ctr->acc[3], cnt);
+    g_add(&rd.ctr->acc[2], ke);
+    g_add(&rd.ctr->acc[3], cnt);
   }
 }
 

@@ -21,7 +21,7 @@
 namespace pic {
 
 // columns and particles the pending injection of this step creates
-__device__ __forceinline__ void pending(const RunDev& rd, const Counters& c, long long& kend,
+__device__ __forceinline__ void pending(RunC& rd, const PIC_G Counters& c, long long& kend,
                                         long long& nnew) {
   if (rd.open) {
     const double shift = rd.beta_b * ((double)c.step * rd.dt) / rd.dz;
@@ -35,7 +35,7 @@ __device__ __forceinline__ void pending(const RunDev& rd, const Counters& c, lon
 }
 
 template <int DIM>
-__device__ __forceinline__ int tile_of(const RunDev& rd, int c) {
+__device__ __forceinline__ int tile_of(RunC& rd, int c) {
   using T = Tile<DIM>;
   const int tz = cell_k(c) >> T::LZ;
   const int tx = cell_i(c) >> T::LX;
@@ -45,7 +45,7 @@ __device__ __forceinline__ int tile_of(const RunDev& rd, int c) {
 
 // wavefront-aggregated atomic add of 1 per active lane to base[key];
 // returns the lane's slot (old value + rank among equal keys)
-__device__ __forceinline__ int wave_agg_add(int* base, int key, bool active) {
+__device__ __forceinline__ int wave_agg_add(PIC_G int* base, int key, bool active) {
   const int lane = threadIdx.x & 63;
   unsigned long long pend = __ballot(active);
   int slot = 0;
@@ -54,7 +54,7 @@ __device__ __forceinline__ int wave_agg_add(int* base, int key, bool active) {
     const int lkey = __shfl(key, leader);
     const unsigned long long m = __ballot(active && key == lkey);
     int b = 0;
-    if (lane == leader) b = atomicAdd(base + lkey, __popcll(m));
+    if (lane == leader) b = g_add(base + lkey, (int)__popcll(m));
     b = __shfl(b, leader);
     if ((m >> lane) & 1ull) slot = b + __popcll(m & ((1ull << lane) - 1ull));
     pend &= ~m;
@@ -68,8 +68,8 @@ __global__ __launch_bounds__(256) void k_inject(const BatchTable* __restrict__ b
   const XcdSplit xs(bt->injblk);
   for (long long w = xs.beg; w < xs.end; w += xs.stride) {
     const int r = __builtin_amdgcn_readfirstlane(locate(bt->pre_injblk, bt->n, w));
-    const RunDev& rd = *bt->run[r];
-    const Counters& c = *rd.ctr;
+    RunC& rd = *bt->run[r];
+    const PIC_G Counters& c = *rd.ctr;
     if (!sort_due(c, rd.inject_every)) continue;
     long long kend, nnew;
     pending(rd, c, kend, nnew);
@@ -83,7 +83,7 @@ __global__ __launch_bounds__(256) void k_inject(const BatchTable* __restrict__ b
       if (q >= nnew) break;
       const long long slot = c.n_slots + q;
       if (slot >= rd.capacity) {
-        atomicOr(&rd.ctr->err, 2u);
+        g_or(&rd.ctr->err, 2u);
         break;
       }
       // slot outermost within a column: consecutive new particles lie in
@@ -142,8 +142,8 @@ __global__ __launch_bounds__(256) void k_count(const BatchTable* __restrict__ bt
   const XcdSplit xs(bt->partblk);
   for (long long w = xs.beg; w < xs.end; w += xs.stride) {
     const int r = __builtin_amdgcn_readfirstlane(locate(bt->pre_partblk, bt->n, w));
-    const RunDev& rd = *bt->run[r];
-    const Counters& c = *rd.ctr;
+    RunC& rd = *bt->run[r];
+    const PIC_G Counters& c = *rd.ctr;
     if (!sort_due(c, rd.inject_every)) continue;
     long long kend, nnew;
     pending(rd, c, kend, nnew);
@@ -166,8 +166,8 @@ __global__ __launch_bounds__(256) void k_count(const BatchTable* __restrict__ bt
 // ------------------------------------------------------------------ scan
 __global__ __launch_bounds__(1024) void k_scan(const BatchTable* __restrict__ bt) {
   if ((int)blockIdx.x >= bt->n) return;
-  const RunDev& rd = *bt->run[blockIdx.x];
-  Counters* c = rd.ctr;
+  RunC& rd = *bt->run[blockIdx.x];
+  PIC_G Counters* c = rd.ctr;
   if (!sort_due(*c, rd.inject_every)) return;
   __shared__ int wsum[16];
   __shared__ int carry_s;
@@ -222,8 +222,8 @@ __global__ __launch_bounds__(256) void k_scatter(const BatchTable* __restrict__ 
   const XcdSplit xs(bt->partblk);
   for (long long w = xs.beg; w < xs.end; w += xs.stride) {
     const int r = __builtin_amdgcn_readfirstlane(locate(bt->pre_partblk, bt->n, w));
-    const RunDev& rd = *bt->run[r];
-    const Counters& c = *rd.ctr;
+    RunC& rd = *bt->run[r];
+    const PIC_G Counters& c = *rd.ctr;
     if (!sort_due(c, rd.inject_every)) continue;
     long long kend, nnew;
     pending(rd, c, kend, nnew);
@@ -258,8 +258,8 @@ __global__ __launch_bounds__(256) void k_scatter(const BatchTable* __restrict__ 
 __global__ void k_commit(const BatchTable* __restrict__ bt) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= bt->n) return;
-  const RunDev& rd = *bt->run[r];
-  Counters* c = rd.ctr;
+  RunC& rd = *bt->run[r];
+  PIC_G Counters* c = rd.ctr;
   if (!sort_due(*c, rd.inject_every)) return;
   long long kend, nnew;
   pending(rd, *c, kend, nnew);

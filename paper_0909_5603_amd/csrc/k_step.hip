@@ -122,123 +122,127 @@ __device__ __forceinline__ int carry(R& o) {
   return 0;
 }
 
+// A current contribution x, already in fixed-point units, as a 64-bit
+// integer.  Split precision: |x| < 2^30 by the choice of the scale, one
+// v_cvt_rpi_i32_f32 (floor(x + 1/2)) and a sign extension.  FP64: |x| < 2^51,
+// adding 1.5 * 2^52 leaves the rounded integer in the low mantissa bits.
+__device__ __forceinline__ long long fixq(float x) {
+  int r;
+  asm("v_cvt_rpi_i32_f32 %0, %1" : "=v"(r) : "v"(x));
+  return (long long)r;
+}
+__device__ __forceinline__ long long fixq(double x) { return to_fixed(x, 1.0); }
+
 // Charge-conserving current of one particle, linear shape (Esirkepov 2001),
 // factored as J = c P[a] F(b,c): P is the running sum of the shape change
 // along the current's direction and F the time-averaged shape across it.
-// Contributions are converted to 64-bit fixed point (to_fixed) and handed
-// to add(comp, dk, di, dj, q) with offsets from the particle's old cell.
-// NX, NY = nodes spanned across x and y: 3 when some lane of the wavefront
-// crossed a cell boundary in that dimension, otherwise 2 (the third node and
-// the second face carry exact zeros then and are not visited).
-template <typename R, int NX, int NY, class A>
-__device__ __forceinline__ void dep3(const Dep1<R>& Z, const Dep1<R>& X, const Dep1<R>& Y, double czS,
-                                     double cxS, double cyS, A&& add) {
+// The coefficient c times the fixed-point scale is folded into P (cz, cx, cy
+// below), and add(comp, a, b, c, q) receives node offsets from the start of
+// the particle's 3-node window.  NXY = nodes visited across x and y: 3 when
+// some lane of the wavefront crossed a cell boundary in x or y, else 2 (the
+// third node and the second face then carry exact zeros).  Zero contributions are added like any other: a branch per
+// contribution costs more than the LDS atomic it saves.
+template <typename R, int NXY, class A>
+__device__ __forceinline__ void dep3(const Dep1<R>& Z, const Dep1<R>& X, const Dep1<R>& Y, R cz, R cx,
+                                     R cy, A&& add) {
   R Ay[3], By[3], Ax[3], Bx[3];
 #pragma unroll
-  for (int c = 0; c < 3; ++c) {
+  for (int c = 0; c < NXY; ++c) {
     Ay[c] = Y.S0[c] + R(0.5) * Y.DS[c];
     By[c] = R(0.5) * Y.S0[c] + R(1.0 / 3.0) * Y.DS[c];
     Ax[c] = X.S0[c] + R(0.5) * X.DS[c];
     Bx[c] = R(0.5) * X.S0[c] + R(1.0 / 3.0) * X.DS[c];
   }
+  const R pz0 = Z.P[0] * cz, pz1 = Z.P[1] * cz;
   // J_z(face a; node b, c) = cz P_z[a] (S0x Ay + DSx By)
 #pragma unroll
-  for (int b = 0; b < NX; ++b)
+  for (int b = 0; b < NXY; ++b)
 #pragma unroll
-    for (int c = 0; c < NY; ++c) {
+    for (int c = 0; c < NXY; ++c) {
       const R f = X.S0[b] * Ay[c] + X.DS[b] * By[c];
-#pragma unroll
-      for (int a = 0; a < 2; ++a) {
-        const long long q = to_fixed(Z.P[a] * f, czS);
-        if (q != 0) add(2, Z.base + a, X.base + b, Y.base + c, q);
-      }
+      add(2, 0, b, c, fixq(pz0 * f));
+      add(2, 1, b, c, fixq(pz1 * f));
     }
   // J_x(node a; face b; node c) = cx P_x[b] (S0z Ay + DSz By)
+  R px[2], py[2];
+#pragma unroll
+  for (int b = 0; b < NXY - 1; ++b) {
+    px[b] = X.P[b] * cx;
+    py[b] = Y.P[b] * cy;
+  }
 #pragma unroll
   for (int a = 0; a < 3; ++a)
 #pragma unroll
-    for (int c = 0; c < NY; ++c) {
+    for (int c = 0; c < NXY; ++c) {
       const R f = Z.S0[a] * Ay[c] + Z.DS[a] * By[c];
 #pragma unroll
-      for (int b = 0; b < NX - 1; ++b) {
-        const long long q = to_fixed(X.P[b] * f, cxS);
-        if (q != 0) add(0, Z.base + a, X.base + b, Y.base + c, q);
-      }
+      for (int b = 0; b < NXY - 1; ++b) add(0, a, b, c, fixq(px[b] * f));
     }
   // J_y(node a, b; face c) = cy P_y[c] (S0z Ax + DSz Bx)
 #pragma unroll
   for (int a = 0; a < 3; ++a)
 #pragma unroll
-    for (int b = 0; b < NX; ++b) {
+    for (int b = 0; b < NXY; ++b) {
       const R f = Z.S0[a] * Ax[b] + Z.DS[a] * Bx[b];
 #pragma unroll
-      for (int c = 0; c < NY - 1; ++c) {
-        const long long q = to_fixed(Y.P[c] * f, cyS);
-        if (q != 0) add(1, Z.base + a, X.base + b, Y.base + c, q);
-      }
+      for (int c = 0; c < NXY - 1; ++c) add(1, a, b, c, fixq(py[c] * f));
     }
 }
 
 // 2D3V: J_z = cz P_z (S0x + DSx/2), J_x = cx P_x (S0z + DSz/2), and the
-// out-of-plane J_y = q w v_y times the time-averaged node shape.
+// out-of-plane J_y = q w v_y times the time-averaged node shape (cyv = its
+// coefficient times v_y).
 template <typename R, int NX, class A>
-__device__ __forceinline__ void dep2(const Dep1<R>& Z, const Dep1<R>& X, double czS, double cxS,
-                                     double cyvS, A&& add) {
+__device__ __forceinline__ void dep2(const Dep1<R>& Z, const Dep1<R>& X, R cz, R cx, R cyv, A&& add) {
   R Ax[3], Bx[3];
 #pragma unroll
-  for (int b = 0; b < 3; ++b) {
+  for (int b = 0; b < NX; ++b) {
     Ax[b] = X.S0[b] + R(0.5) * X.DS[b];
     Bx[b] = R(0.5) * X.S0[b] + R(1.0 / 3.0) * X.DS[b];
   }
+  const R pz0 = Z.P[0] * cz, pz1 = Z.P[1] * cz;
 #pragma unroll
-  for (int b = 0; b < NX; ++b)
+  for (int b = 0; b < NX; ++b) {
+    add(2, 0, b, 0, fixq(pz0 * Ax[b]));
+    add(2, 1, b, 0, fixq(pz1 * Ax[b]));
+  }
+  R px[2];
 #pragma unroll
-    for (int a = 0; a < 2; ++a) {
-      const long long q = to_fixed(Z.P[a] * Ax[b], czS);
-      if (q != 0) add(2, Z.base + a, X.base + b, 0, q);
-    }
+  for (int b = 0; b < NX - 1; ++b) px[b] = X.P[b] * cx;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     const R az = Z.S0[a] + R(0.5) * Z.DS[a];
 #pragma unroll
-    for (int b = 0; b < NX - 1; ++b) {
-      const long long q = to_fixed(X.P[b] * az, cxS);
-      if (q != 0) add(0, Z.base + a, X.base + b, 0, q);
-    }
+    for (int b = 0; b < NX - 1; ++b) add(0, a, b, 0, fixq(px[b] * az));
   }
 #pragma unroll
-  for (int a = 0; a < 3; ++a)
+  for (int a = 0; a < 3; ++a) {
+    const R sa = Z.S0[a] * cyv, da = Z.DS[a] * cyv;
 #pragma unroll
-    for (int b = 0; b < NX; ++b) {
-      const long long q = to_fixed(Z.S0[a] * Ax[b] + Z.DS[a] * Bx[b], cyvS);
-      if (q != 0) add(1, Z.base + a, X.base + b, 0, q);
-    }
+    for (int b = 0; b < NX; ++b) add(1, a, b, 0, fixq(sa * Ax[b] + da * Bx[b]));
+  }
 }
 
 template <int DIM, typename R, class A>
-__device__ __forceinline__ void deposit(const Dep1<R>* d, const int* cr, double czS, double cxS,
-                                        double cyS, double cyvS, A&& add) {
-  // wavefront-uniform: does any active lane cross a cell boundary in x / y?
-  const bool anyx = __any(cr[1] != 0);
+__device__ __forceinline__ void deposit(const Dep1<R>* d, const int* cr, R cz, R cx, R cy, R cyv, A&& add) {
+  // wavefront-uniform: does any active lane cross a cell boundary in x or y?
   if constexpr (DIM == 3) {
-    const bool anyy = __any(cr[2] != 0);
-    if (anyx) {
-      if (anyy) dep3<R, 3, 3>(d[0], d[1], d[2], czS, cxS, cyS, add);
-      else dep3<R, 3, 2>(d[0], d[1], d[2], czS, cxS, cyS, add);
-    } else {
-      if (anyy) dep3<R, 2, 3>(d[0], d[1], d[2], czS, cxS, cyS, add);
-      else dep3<R, 2, 2>(d[0], d[1], d[2], czS, cxS, cyS, add);
-    }
+    if (__any(cr[1] != 0 || cr[2] != 0))
+      dep3<R, 3>(d[0], d[1], d[2], cz, cx, cy, add);
+    else
+      dep3<R, 2>(d[0], d[1], d[2], cz, cx, cy, add);
   } else {
-    if (anyx) dep2<R, 3>(d[0], d[1], czS, cxS, cyvS, add);
-    else dep2<R, 2>(d[0], d[1], czS, cxS, cyvS, add);
+    if (__any(cr[1] != 0))
+      dep2<R, 3>(d[0], d[1], cz, cx, cyv, add);
+    else
+      dep2<R, 2>(d[0], d[1], cz, cx, cyv, add);
   }
 }
 
 // E value with HBM index handling (zero outside an open z range).  Indices
 // are at most a few cells outside the box, so one correction wraps them.
 template <int DIM, typename R>
-__device__ __forceinline__ R gE(const RunDev& rd, R* const* E, int comp, int k, int i, int j) {
+__device__ __forceinline__ R gE(RunC& rd, const Arr3<R>& E, int comp, int k, int i, int j) {
   i = wrap1(i, rd.nx);
   j = DIM == 3 ? wrap1(j, rd.ny) : 0;
   if (rd.open) {
@@ -252,7 +256,7 @@ __device__ __forceinline__ R gE(const RunDev& rd, R* const* E, int comp, int k, 
 // field value at integer time n for the HBM path: E directly, B advanced
 // from n-1/2 on the fly
 template <int DIM, typename R>
-__device__ R fetch_hbm(const RunDev& rd, R* const* E, R* const* B, int comp, int k, int i, int j) {
+__device__ R fetch_hbm(RunC& rd, const Arr3<R>& E, const Arr3<R>& B, int comp, int k, int i, int j) {
   if (comp < 3) return gE<DIM, R>(rd, E, comp, k, i, j);
   int ii = wrap1(i, rd.nx), jj = DIM == 3 ? wrap1(j, rd.ny) : 0, kk = k;
   if (rd.open) {
@@ -276,7 +280,7 @@ __device__ R fetch_hbm(const RunDev& rd, R* const* E, R* const* B, int comp, int
 }
 
 template <int DIM>
-__device__ __forceinline__ void add_hbm(const RunDev& rd, int fb, int comp, int k, int i, int j, long long q) {
+__device__ __forceinline__ void add_hbm(RunC& rd, int fb, int comp, int k, int i, int j, long long q) {
   i = wrap1(i, rd.nx);
   j = DIM == 3 ? wrap1(j, rd.ny) : 0;
   if (rd.open) {
@@ -284,8 +288,7 @@ __device__ __forceinline__ void add_hbm(const RunDev& rd, int fb, int comp, int 
   } else {
     k = wrap1(k, rd.nz);
   }
-  atomicAdd(reinterpret_cast<unsigned long long*>(rd.J[fb][comp]) + gidx(rd, k, i, j),
-            (unsigned long long)q);
+  g_add((PIC_G unsigned long long*)rd.J[fb][comp] + gidx(rd, k, i, j), (unsigned long long)q);
 }
 
 // ------------------------------------------------------------------ particles
@@ -293,11 +296,11 @@ __device__ __forceinline__ void add_hbm(const RunDev& rd, int fb, int comp, int 
 template <typename R>
 struct PConst {
   R eps, cdz, cdx, cdy;
-  double czS, cxS, cyS, cyvS;  // current coefficients times the fixed-point scale
+  R cz, cx, cy, cyv;  // current coefficients times the fixed-point scale
 };
 
 template <int DIM, typename R>
-__device__ __forceinline__ PConst<R> pconst(const RunDev& rd) {
+__device__ __forceinline__ PConst<R> pconst(RunC& rd) {
   PConst<R> K;
   K.eps = R(-0.5 * rd.dt);
   K.cdz = R(rd.dt / rd.dz);
@@ -305,26 +308,27 @@ __device__ __forceinline__ PConst<R> pconst(const RunDev& rd) {
   K.cdy = R(rd.dt / rd.dy);
   const double S = rd.jscale;
   if (DIM == 3) {
-    K.czS = S * rd.weight / (rd.dx * rd.dy * rd.dt);
-    K.cxS = S * rd.weight / (rd.dz * rd.dy * rd.dt);
-    K.cyS = S * rd.weight / (rd.dz * rd.dx * rd.dt);
+    K.cz = R(S * rd.weight / (rd.dx * rd.dy * rd.dt));
+    K.cx = R(S * rd.weight / (rd.dz * rd.dy * rd.dt));
+    K.cy = R(S * rd.weight / (rd.dz * rd.dx * rd.dt));
   } else {
-    K.czS = S * rd.weight / (rd.dx * rd.dt);
-    K.cxS = S * rd.weight / (rd.dz * rd.dt);
-    K.cyS = 0.0;
+    K.cz = R(S * rd.weight / (rd.dx * rd.dt));
+    K.cx = R(S * rd.weight / (rd.dz * rd.dt));
+    K.cy = R(0);
   }
-  K.cyvS = -S * rd.weight / (rd.dz * rd.dx);
+  K.cyv = R(-S * rd.weight / (rd.dz * rd.dx));
   return K;
 }
 
 // Gather, push, move and deposit of one particle.  o[] holds the old
 // offsets on entry and the new ones on exit, cr[] receives the cell carries.
-// fetch(comp, dk, di, dj) and add(comp, dk, di, dj, v) address fields and
-// currents relative to the particle's old cell.  Returns true if the new
-// momentum is not finite.
+// fetch(comp, dk, di, dj) addresses fields relative to the particle's old
+// cell; adder(dk, di, dj) returns the current accumulator add(comp, a, b, c,
+// q) of the deposit window that starts at (dk, di, dj) from the old cell.
+// Returns true if the new momentum is not finite.
 template <int DIM, typename R, int PUSHER, class F, class A>
 __device__ __forceinline__ bool advance(const PConst<R>& K, R* o, R& ux, R& uy, R& uz, int* cr,
-                                        F&& fetch, A&& add) {
+                                        F&& fetch, A&& adder) {
   W1<R> wt[3];
   wt[0] = weights(o[0]);
   wt[1] = weights(o[1]);
@@ -353,7 +357,8 @@ __device__ __forceinline__ bool advance(const PConst<R>& K, R* o, R& ux, R& uy, 
   dd[0] = dep1(o[0], on[0], cr[0]);
   dd[1] = dep1(o[1], on[1], cr[1]);
   if (DIM == 3) dd[2] = dep1(o[2], on[2], cr[2]);
-  deposit<DIM, R>(dd, cr, K.czS, K.cxS, K.cyS, K.cyvS * (double)(uy * ig), add);
+  deposit<DIM, R>(dd, cr, K.cz, K.cx, K.cy, K.cyv * (uy * ig),
+                  adder(dd[0].base, dd[1].base, DIM == 3 ? dd[2].base : 0));
   o[0] = on[0];
   o[1] = on[1];
   o[2] = on[2];
@@ -362,7 +367,7 @@ __device__ __forceinline__ bool advance(const PConst<R>& K, R* o, R& ux, R& uy, 
 
 // new packed cell after the carries; removal at the open z ends
 template <int DIM>
-__device__ __forceinline__ int new_cell(const RunDev& rd, int k, int i, int j, const int* cr, bool& dead,
+__device__ __forceinline__ int new_cell(RunC& rd, int k, int i, int j, const int* cr, bool& dead,
                                         int& k1, int& i1, int& j1) {
   k1 = k + cr[0];
   i1 = wrap1(i + cr[1], rd.nx);
@@ -381,16 +386,24 @@ __global__ __launch_bounds__(BLOCK) void k_particles(const BatchTable* __restric
   constexpr int WZM = T::WZ, WXM = T::WX, WYM = T::WY;
   constexpr int WV = WZM * WXM * WYM;
   constexpr int SY = (DIM == 3) ? WZM * WXM : 0;  // LDS stride of y
-  __shared__ R sF[6][WV];           // Ex Ey Ez Bx By Bz of the tile window
-  __shared__ long long sJ[3][WV];   // Jx Jy Jz, 64-bit fixed point
-  __shared__ int sred[6][BLOCK / 64];
+  // LDS: the current window first, so that every deposit address is one
+  // per-particle base plus an immediate offset below 64 KiB
+  struct Smem {
+    long long J[3][WV];  // Jx Jy Jz, 64-bit fixed point
+    R F[6][WV];          // Ex Ey Ez Bx By Bz of the tile window
+    int red[6][BLOCK / 64];
+  };
+  __shared__ Smem sm;
+  auto& sJ = sm.J;
+  auto& sF = sm.F;
+  auto& sred = sm.red;
 
   const XcdSplit xs(bt->tiles);
   for (long long w = xs.beg; w < xs.end; w += xs.stride) {
     const int r = __builtin_amdgcn_readfirstlane(locate(bt->pre_tiles, bt->n, w));
-    const RunDev& rd = *bt->run[r];
+    RunC& rd = *bt->run[r];
     const int tile = (int)(w - bt->pre_tiles[r]);
-    const Counters& ctr = *rd.ctr;
+    const PIC_G Counters& ctr = *rd.ctr;
     const int pb = ctr.pbuf, fb = ctr.fbuf, bb = ctr.bbuf, fresh = ctr.fresh;
     const int nx = rd.nx, ny = rd.ny, nz = rd.nz, nzf = rd.nzf;
     const bool open = rd.open != 0;
@@ -400,7 +413,7 @@ __global__ __launch_bounds__(BLOCK) void k_particles(const BatchTable* __restric
     const int tx = rest % ntx, ty = rest / ntx;
     const int t0[3] = {tz * T::TZ, tx * T::TX, ty * T::TY};
     const long long p0 = rd.tile_start[tile], p1 = rd.tile_start[tile + 1];
-    int* bbw = rd.bbox[bb ^ 1] + 6 * tile;
+    PIC_G int* bbw = rd.bbox[bb ^ 1] + 6 * tile;
     if (p0 >= p1) {
       if (threadIdx.x == 0) {
         bbw[0] = bbw[1] = bbw[2] = 1 << 20;
@@ -410,7 +423,7 @@ __global__ __launch_bounds__(BLOCK) void k_particles(const BatchTable* __restric
     }
     int lo[3] = {0, 0, 0}, hi[3] = {T::TZ - 1, T::TX - 1, T::TY - 1};
     if (!fresh) {
-      const int* bbr = rd.bbox[bb] + 6 * tile;
+      const PIC_G int* bbr = rd.bbox[bb] + 6 * tile;
       if (bbr[0] <= bbr[3]) {
         for (int d = 0; d < 3; ++d) {
           lo[d] = bbr[d];
@@ -425,8 +438,8 @@ __global__ __launch_bounds__(BLOCK) void k_particles(const BatchTable* __restric
     for (int d = 0; d < 3; ++d) w0[d] = t0[d] + lo[d] - 1;
     if (DIM == 2) w0[2] = 0;
 
-    R* const* Eg = reinterpret_cast<R* const*>(rd.E[fb]);
-    R* const* Bg = reinterpret_cast<R* const*>(rd.B[fb]);
+    const Arr3<R> Eg = PIC_ARR3(R, rd.E[fb]);
+    const Arr3<R> Bg = PIC_ARR3(R, rd.B[fb]);
     const R dt = R(rd.dt);
 
     // ---- stage E^n and B^{n-1/2} of the window; clear the current window.
@@ -515,13 +528,13 @@ __global__ __launch_bounds__(BLOCK) void k_particles(const BatchTable* __restric
 
     // ---- particles whose stencil lies in the window; the others are queued
     // for the HBM kernel
-    int* __restrict__ cellp = rd.cell[pb];
-    R* __restrict__ o0p = fptr<R>(rd.off[pb][0]);
-    R* __restrict__ o1p = fptr<R>(rd.off[pb][1]);
-    R* __restrict__ o2p = fptr<R>(rd.off[pb][2]);
-    R* __restrict__ uxp = fptr<R>(rd.u[pb][0]);
-    R* __restrict__ uyp = fptr<R>(rd.u[pb][1]);
-    R* __restrict__ uzp = fptr<R>(rd.u[pb][2]);
+    PIC_G int* __restrict__ cellp = rd.cell[pb];
+    PIC_G R* __restrict__ o0p = fptr<R>(rd.off[pb][0]);
+    PIC_G R* __restrict__ o1p = fptr<R>(rd.off[pb][1]);
+    PIC_G R* __restrict__ o2p = fptr<R>(rd.off[pb][2]);
+    PIC_G R* __restrict__ uxp = fptr<R>(rd.u[pb][0]);
+    PIC_G R* __restrict__ uyp = fptr<R>(rd.u[pb][1]);
+    PIC_G R* __restrict__ uzp = fptr<R>(rd.u[pb][2]);
     const PConst<R> K = pconst<DIM, R>(rd);
     const int gz = rd.gz, gx = rd.gx, gy = rd.gy;
     int bmin0 = 1 << 20, bmin1 = 1 << 20, bmin2 = 1 << 20;
@@ -584,7 +597,7 @@ __global__ __launch_bounds__(BLOCK) void k_particles(const BatchTable* __restric
       const bool fast = wk >= 1 && wk <= Wd[0] - 3 && wi >= 1 && wi <= Wd[1] - 3 &&
                         (DIM == 2 || (wj >= 1 && wj <= Wd[2] - 3));
       if (!fast) {
-        const unsigned e = atomicAdd(&rd.ctr->n_slowq, 1u);
+        const unsigned e = g_add(&rd.ctr->n_slowq, 1u);
         if (e < (unsigned long long)rd.capacity) rd.slowq[e] = (int)p;
         continue;
       }
@@ -593,9 +606,11 @@ __global__ __launch_bounds__(BLOCK) void k_particles(const BatchTable* __restric
       bad |= advance<DIM, R, PUSHER>(
           K, o, ux, uy, uz, cr,
           [&](int comp, int dk, int di, int dj) -> R { return sF[comp][base + dk + di * WZM + dj * SY]; },
-          [&](int comp, int dk, int di, int dj, long long q) {
-            atomicAdd(reinterpret_cast<unsigned long long*>(&sJ[comp][base + dk + di * WZM + dj * SY]),
-                      (unsigned long long)q);
+          [&](int zb, int xb, int yb) {
+            unsigned long long* jw = reinterpret_cast<unsigned long long*>(&sJ[0][base + zb + xb * WZM + yb * SY]);
+            return [jw](int comp, int a, int b, int c, long long q) {
+              atomicAdd(jw + comp * WV + a + b * WZM + c * SY, (unsigned long long)q);
+            };
           });
       bool dead;
       int k1, i1, j1;
@@ -620,7 +635,7 @@ __global__ __launch_bounds__(BLOCK) void k_particles(const BatchTable* __restric
         }
       }
     }
-    if (bad) atomicOr(&rd.ctr->err, 1u);
+    if (bad) g_or(&rd.ctr->err, 1u);
     // ---- bounding box of the new positions
 #pragma unroll
     for (int m = 32; m >= 1; m >>= 1) {
@@ -667,10 +682,10 @@ __global__ __launch_bounds__(BLOCK) void k_particles(const BatchTable* __restric
         gk = wrap2(gk, nz);
       }
       const long long g = ((long long)gj * nx + gi) * nzf + gk;
-      unsigned long long* const* Jg = reinterpret_cast<unsigned long long* const*>(rd.J[fb]);
-      if (zn && jx != 0) atomicAdd(Jg[0] + g, (unsigned long long)jx);
-      if (zn && jy != 0) atomicAdd(Jg[1] + g, (unsigned long long)jy);
-      if (zh && jz != 0) atomicAdd(Jg[2] + g, (unsigned long long)jz);
+      const Arr3<unsigned long long> Jg = PIC_ARR3(unsigned long long, rd.J[fb]);
+      if (zn && jx != 0) g_add(Jg[0] + g, (unsigned long long)jx);
+      if (zn && jy != 0) g_add(Jg[1] + g, (unsigned long long)jy);
+      if (zh && jz != 0) g_add(Jg[2] + g, (unsigned long long)jz);
     }
   }
 }
@@ -682,13 +697,13 @@ template <int DIM, typename R, int PUSHER>
 __global__ __launch_bounds__(256) void k_particles_hbm(const BatchTable* __restrict__ bt) {
   using T = Tile<DIM>;
   for (int r = 0; r < bt->n; ++r) {
-    const RunDev& rd = *bt->run[r];
-    const Counters& ctr = *rd.ctr;
+    RunC& rd = *bt->run[r];
+    const PIC_G Counters& ctr = *rd.ctr;
     const long long n = min((long long)ctr.n_slowq, rd.capacity);
     if (n == 0) continue;
     const int pb = ctr.pbuf, fb = ctr.fbuf, bb = ctr.bbuf;
-    R* const* Eg = reinterpret_cast<R* const*>(rd.E[fb]);
-    R* const* Bg = reinterpret_cast<R* const*>(rd.B[fb]);
+    const Arr3<R> Eg = PIC_ARR3(R, rd.E[fb]);
+    const Arr3<R> Bg = PIC_ARR3(R, rd.B[fb]);
     const PConst<R> K = pconst<DIM, R>(rd);
     for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n;
          e += (long long)gridDim.x * blockDim.x) {
@@ -706,10 +721,13 @@ __global__ __launch_bounds__(256) void k_particles_hbm(const BatchTable* __restr
           [&](int comp, int dk, int di, int dj) -> R {
             return fetch_hbm<DIM, R>(rd, Eg, Bg, comp, k + dk, i + di, j + dj);
           },
-          [&](int comp, int dk, int di, int dj, long long q) {
-            add_hbm<DIM>(rd, fb, comp, k + dk, i + di, j + dj, q);
+          [&](int zb, int xb, int yb) {
+            const int kw = k + zb, iw = i + xb, jw = j + yb;
+            return [&rd, fb, kw, iw, jw](int comp, int a, int b, int c, long long q) {
+              add_hbm<DIM>(rd, fb, comp, kw + a, iw + b, jw + c, q);
+            };
           });
-      if (bad) atomicOr(&rd.ctr->err, 1u);
+      if (bad) g_or(&rd.ctr->err, 1u);
       bool dead;
       int k1, i1, j1;
       rd.cell[pb][p] = new_cell<DIM>(rd, k, i, j, cr, dead, k1, i1, j1);
@@ -729,17 +747,17 @@ __global__ __launch_bounds__(256) void k_particles_hbm(const BatchTable* __restr
         const int tile = lo;
         const int tz = tile % rd.ntz, rest = tile / rd.ntz;
         const int tx = rest % rd.ntx, ty = rest / rd.ntx;
-        int* bbw = rd.bbox[bb ^ 1] + 6 * tile;
+        PIC_G int* bbw = rd.bbox[bb ^ 1] + 6 * tile;
         const int nk = rd.open ? k1 - tz * T::TZ : relw(k1, tz * T::TZ, rd.nz, rd.gz);
         const int ni = relw(i1, tx * T::TX, rd.nx, rd.gx);
-        atomicMin(bbw + 0, nk);
-        atomicMax(bbw + 3, nk);
-        atomicMin(bbw + 1, ni);
-        atomicMax(bbw + 4, ni);
+        g_min(bbw + 0, nk);
+        g_max(bbw + 3, nk);
+        g_min(bbw + 1, ni);
+        g_max(bbw + 4, ni);
         if (DIM == 3) {
           const int nj = relw(j1, ty * T::TY, rd.ny, rd.gy);
-          atomicMin(bbw + 2, nj);
-          atomicMax(bbw + 5, nj);
+          g_min(bbw + 2, nj);
+          g_max(bbw + 5, nj);
         }
       }
     }
@@ -754,23 +772,57 @@ __global__ __launch_bounds__(256) void k_particles_hbm(const BatchTable* __restr
 //            and clears the current buffer of the next step (J[fb^1])
 //   k_mur:   first-order Mur on the tangential E at the open z ends, from
 //            E^n (still in E[fb]) and the interior E^{n+1}.
-template <int DIM, typename R>
-struct FieldView {
-  int nzf, nx, ny, nz;
-  bool open;
-  __device__ __forceinline__ int wx(int i) const { return i < 0 ? i + nx : (i >= nx ? i - nx : i); }
-  __device__ __forceinline__ int wy(int j) const {
-    return DIM == 3 ? (j < 0 ? j + ny : (j >= ny ? j - ny : j)) : 0;
-  }
-  // z index of component c, or -1 outside the open range
-  __device__ __forceinline__ int zk(int c, int k) const {
-    if (open) return (k >= 0 && k < (stag(c, 0) ? nz : nz + 1)) ? k : -1;
-    return k < 0 ? k + nz : (k >= nz ? k - nz : k);
-  }
-  __device__ __forceinline__ R at(R* const* F, int c, int fc, int k, int i, int j) const {
-    const int z = zk(fc, k);
-    if (z < 0) return R(0);
-    return F[c][((long long)wy(j) * nx + wx(i)) * nzf + z];
+// A grid point q = (j nx + i) nzf + k of one field work item and the flat
+// indices of its six neighbours.  The work item's first point is decoded
+// once (uniform), each thread then steps from it, so no thread divides;
+// indices are 32-bit (a run holds fewer than 2^31 points).  Neighbour values
+// outside the open z range of their component read as zero.
+template <int DIM>
+struct FieldPt {
+  unsigned q, qzp, qzm, qxp, qxm, qyp, qym;
+  int k;
+  bool zp_n, zp_h, zm_ok, c_h;  // k+1 valid for node / half components, k-1 valid, k valid for half
+
+  __device__ __forceinline__ bool init(RunC& rd, long long item) {
+    const unsigned nzf = (unsigned)rd.nzf, nx = (unsigned)rd.nx, ny = (unsigned)rd.ny, nz = (unsigned)rd.nz;
+    const unsigned q0 = (unsigned)item * CELL_BLOCK;
+    const unsigned t0 = q0 / nzf;
+    unsigned kk = q0 - t0 * nzf + threadIdx.x, t = t0;
+    while (kk >= nzf) {
+      kk -= nzf;
+      ++t;
+    }
+    const unsigned j0 = t0 / nx;
+    unsigned i = t0 - j0 * nx + (t - t0), j = j0;
+    while (i >= nx) {
+      i -= nx;
+      ++j;
+    }
+    q = q0 + threadIdx.x;
+    if (q >= (unsigned)rd.npts) return false;
+    k = (int)kk;
+    const unsigned sx = nzf, sy = nx * nzf;
+    qxp = i + 1 == nx ? q - (nx - 1) * sx : q + sx;
+    qxm = i == 0 ? q + (nx - 1) * sx : q - sx;
+    if (DIM == 3) {
+      qyp = j + 1 == ny ? q - (ny - 1) * sy : q + sy;
+      qym = j == 0 ? q + (ny - 1) * sy : q - sy;
+    } else {
+      qyp = qym = q;
+    }
+    if (rd.open) {
+      qzp = q + 1;
+      qzm = q - 1;
+      zp_n = kk + 1 <= nz;  // nodes 0..nz
+      zp_h = kk + 1 < nz;   // half points 0..nz-1
+      zm_ok = kk >= 1;      // k-1 >= 0 (then k-1 < nz is valid for both)
+      c_h = kk < nz;
+    } else {
+      qzp = kk + 1 == nz ? q + 1 - nz : q + 1;
+      qzm = kk == 0 ? q + nz - 1 : q - 1;
+      zp_n = zp_h = zm_ok = c_h = true;
+    }
+    return true;
   }
 };
 
@@ -779,33 +831,32 @@ __global__ __launch_bounds__(256) void k_bhalf(const BatchTable* __restrict__ bt
   const XcdSplit xs(bt->cellblk);
   for (long long w = xs.beg; w < xs.end; w += xs.stride) {
     const int r = __builtin_amdgcn_readfirstlane(locate(bt->pre_cellblk, bt->n, w));
-    const RunDev& rd = *bt->run[r];
-    const long long q = (w - bt->pre_cellblk[r]) * CELL_BLOCK + threadIdx.x;
-    if (q >= rd.npts) continue;
-    const FieldView<DIM, R> V{rd.nzf, rd.nx, rd.ny, rd.nz, rd.open != 0};
-    const int k = (int)(q % V.nzf);
-    const long long t = q / V.nzf;
-    const int i = (int)(t % V.nx), j = (int)(t / V.nx);
+    RunC& rd = *bt->run[r];
+    FieldPt<DIM> P;
+    if (!P.init(rd, w - bt->pre_cellblk[r])) continue;
     const int fb = rd.ctr->fbuf;
-    R* const* E = reinterpret_cast<R* const*>(rd.E[fb]);
-    R* const* Bm = reinterpret_cast<R* const*>(rd.B[fb]);
-    R* const* Bh = reinterpret_cast<R* const*>(rd.B[fb ^ 1]);
+    const Arr3<R> E = PIC_ARR3(R, rd.E[fb]);
+    const Arr3<R> Bm = PIC_ARR3(R, rd.B[fb]);
+    const Arr3<R> Bh = PIC_ARR3(R, rd.B[fb ^ 1]);
     const R dt = R(rd.dt);
     const R idz = R(1.0 / rd.dz), idx = R(1.0 / rd.dx), idy = DIM == 3 ? R(1.0 / rd.dy) : R(0);
-    const R ex = V.at(E, 0, 0, k, i, j), ey = V.at(E, 1, 1, k, i, j), ez = V.at(E, 2, 2, k, i, j);
-    const R ey_z = V.at(E, 1, 1, k + 1, i, j), ex_z = V.at(E, 0, 0, k + 1, i, j);
-    const R ez_x = V.at(E, 2, 2, k, i + 1, j), ey_x = V.at(E, 1, 1, k, i + 1, j);
+    const unsigned q = P.q;
+    // Ex, Ey on nodes in z, Ez on half points
+    const R ex = E[0][q], ey = E[1][q], ez = P.c_h ? E[2][q] : R(0);
+    const R ey_z = P.zp_n ? E[1][P.qzp] : R(0), ex_z = P.zp_n ? E[0][P.qzp] : R(0);
+    const R ez_x = P.c_h ? E[2][P.qxp] : R(0), ey_x = E[1][P.qxp];
     R ez_y = R(0), ex_y = R(0);
     if (DIM == 3) {
-      ez_y = V.at(E, 2, 2, k, i, j + 1);
-      ex_y = V.at(E, 0, 0, k, i, j + 1);
+      ez_y = P.c_h ? E[2][P.qyp] : R(0);
+      ex_y = E[0][P.qyp];
     }
     const R cx = (ez_y - ez) * idy - (ey_z - ey) * idz;
     const R cy = (ex_z - ex) * idz - (ez_x - ez) * idx;
     const R cz = (ey_x - ey) * idx - (ex_y - ex) * idy;
-    Bh[0][q] = V.zk(3, k) >= 0 ? Bm[0][q] - dt * cx : R(0);
-    Bh[1][q] = V.zk(4, k) >= 0 ? Bm[1][q] - dt * cy : R(0);
-    Bh[2][q] = V.zk(5, k) >= 0 ? Bm[2][q] - dt * cz : R(0);
+    // Bx, By on half points in z, Bz on nodes
+    Bh[0][q] = P.c_h ? Bm[0][q] - dt * cx : R(0);
+    Bh[1][q] = P.c_h ? Bm[1][q] - dt * cy : R(0);
+    Bh[2][q] = Bm[2][q] - dt * cz;
   }
 }
 
@@ -814,35 +865,32 @@ __global__ __launch_bounds__(256) void k_efull(const BatchTable* __restrict__ bt
   const XcdSplit xs(bt->cellblk);
   for (long long w = xs.beg; w < xs.end; w += xs.stride) {
     const int r = __builtin_amdgcn_readfirstlane(locate(bt->pre_cellblk, bt->n, w));
-    const RunDev& rd = *bt->run[r];
-    const long long q = (w - bt->pre_cellblk[r]) * CELL_BLOCK + threadIdx.x;
-    if (q >= rd.npts) continue;
-    const FieldView<DIM, R> V{rd.nzf, rd.nx, rd.ny, rd.nz, rd.open != 0};
-    const int k = (int)(q % V.nzf);
-    const long long t = q / V.nzf;
-    const int i = (int)(t % V.nx), j = (int)(t / V.nx);
+    RunC& rd = *bt->run[r];
+    FieldPt<DIM> P;
+    if (!P.init(rd, w - bt->pre_cellblk[r])) continue;
     const int fb = rd.ctr->fbuf;
-    R* const* E = reinterpret_cast<R* const*>(rd.E[fb]);
-    R* const* En = reinterpret_cast<R* const*>(rd.E[fb ^ 1]);
-    R* const* Bh = reinterpret_cast<R* const*>(rd.B[fb ^ 1]);
-    const long long* const* J = reinterpret_cast<const long long* const*>(rd.J[fb]);
-    long long* const* Jnext = reinterpret_cast<long long* const*>(rd.J[fb ^ 1]);
+    const Arr3<R> E = PIC_ARR3(R, rd.E[fb]);
+    const Arr3<R> En = PIC_ARR3(R, rd.E[fb ^ 1]);
+    const Arr3<R> Bh = PIC_ARR3(R, rd.B[fb ^ 1]);
+    const Arr3<long long> J = PIC_ARR3(long long, rd.J[fb]);
+    const Arr3<long long> Jnext = PIC_ARR3(long long, rd.J[fb ^ 1]);
     const R dt = R(rd.dt);
     const R idz = R(1.0 / rd.dz), idx = R(1.0 / rd.dx), idy = DIM == 3 ? R(1.0 / rd.dy) : R(0);
     const double jinv = rd.jinv;
-    const R bx = V.at(Bh, 0, 3, k, i, j), by = V.at(Bh, 1, 4, k, i, j), bz = V.at(Bh, 2, 5, k, i, j);
-    const R by_z = V.at(Bh, 1, 4, k - 1, i, j), bx_z = V.at(Bh, 0, 3, k - 1, i, j);
-    const R bz_x = V.at(Bh, 2, 5, k, i - 1, j), by_x = V.at(Bh, 1, 4, k, i - 1, j);
+    const unsigned q = P.q;
+    // Bx, By on half points in z (k-1 is a half point whenever k-1 >= 0)
+    const R bx = P.c_h ? Bh[0][q] : R(0), by = P.c_h ? Bh[1][q] : R(0), bz = Bh[2][q];
+    const R by_z = P.zm_ok ? Bh[1][P.qzm] : R(0), bx_z = P.zm_ok ? Bh[0][P.qzm] : R(0);
+    const R bz_x = Bh[2][P.qxm], by_x = P.c_h ? Bh[1][P.qxm] : R(0);
     R bz_y = R(0), bx_y = R(0);
     if (DIM == 3) {
-      bz_y = V.at(Bh, 2, 5, k, i, j - 1);
-      bx_y = V.at(Bh, 0, 3, k, i, j - 1);
+      bz_y = Bh[2][P.qym];
+      bx_y = P.c_h ? Bh[0][P.qym] : R(0);
     }
     const R jx = R((double)J[0][q] * jinv), jy = R((double)J[1][q] * jinv), jz = R((double)J[2][q] * jinv);
-    const bool zn = V.zk(0, k) >= 0, zh = V.zk(2, k) >= 0;
-    En[0][q] = zn ? E[0][q] + dt * ((bz - bz_y) * idy - (by - by_z) * idz - jx) : R(0);
-    En[1][q] = zn ? E[1][q] + dt * ((bx - bx_z) * idz - (bz - bz_x) * idx - jy) : R(0);
-    En[2][q] = zh ? E[2][q] + dt * ((by - by_x) * idx - (bx - bx_y) * idy - jz - R(rd.jion_z)) : R(0);
+    En[0][q] = E[0][q] + dt * ((bz - bz_y) * idy - (by - by_z) * idz - jx);
+    En[1][q] = E[1][q] + dt * ((bx - bx_z) * idz - (bz - bz_x) * idx - jy);
+    En[2][q] = P.c_h ? E[2][q] + dt * ((by - by_x) * idx - (bx - bx_y) * idy - jz - R(rd.jion_z)) : R(0);
     Jnext[0][q] = 0;
     Jnext[1][q] = 0;
     Jnext[2][q] = 0;
@@ -854,15 +902,15 @@ __global__ __launch_bounds__(256) void k_mur(const BatchTable* __restrict__ bt) 
   const XcdSplit xs(bt->cellblk);
   for (long long w = xs.beg; w < xs.end; w += xs.stride) {
     const int r = __builtin_amdgcn_readfirstlane(locate(bt->pre_cellblk, bt->n, w));
-    const RunDev& rd = *bt->run[r];
+    RunC& rd = *bt->run[r];
     if (!rd.open) continue;
     const long long q = (w - bt->pre_cellblk[r]) * CELL_BLOCK + threadIdx.x;
     if (q >= 2 * rd.nperp) continue;
     const int side = (int)(q / rd.nperp);
     const long long col = (q % rd.nperp) * rd.nzf;
     const int fb = rd.ctr->fbuf;
-    R* const* E = reinterpret_cast<R* const*>(rd.E[fb]);
-    R* const* En = reinterpret_cast<R* const*>(rd.E[fb ^ 1]);
+    const Arr3<R> E = PIC_ARR3(R, rd.E[fb]);
+    const Arr3<R> En = PIC_ARR3(R, rd.E[fb ^ 1]);
     const R cm = R((rd.dt - rd.dz) / (rd.dt + rd.dz));
     const int kb = side ? rd.nz : 0, ki = side ? rd.nz - 1 : 1;
     for (int c = 0; c < 2; ++c)
@@ -873,7 +921,7 @@ __global__ __launch_bounds__(256) void k_mur(const BatchTable* __restrict__ bt) 
 __global__ void k_advance(const BatchTable* __restrict__ bt) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= bt->n) return;
-  Counters* c = bt->run[r]->ctr;
+  PIC_G Counters* c = bt->run[r]->ctr;
   c->n_slow += c->n_slowq;
   c->n_slowq = 0;
   c->step += 1;

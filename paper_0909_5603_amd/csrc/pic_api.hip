@@ -45,6 +45,7 @@ constexpr double C_LIGHT = 299792458.0, Q_E = 1.602176634e-19, EPS_0 = 8.8541878
 struct Derived {
   double dt, beta_b, gamma_b, dminus, dplus, skin_um, k0_lab, E0_lab, L_lab, L_boost, zc_boost;
   double weight, dV;
+  double jscale;  // fixed-point scale of the current (a power of two)
   int reservoir, nzf, ztop;
   int ntz, ntx, nty, ntiles;
   long long nperp, npts, capacity, max_new;
@@ -128,13 +129,23 @@ pic_status derive(const pic_lab_params* p, Derived& d) {
   }
   if (d.capacity >= (1LL << 31) - 1) return fail(PIC_EINVAL, "too many particles for one run");
   {
-    // one particle's current contribution is at most w / (dA dt); it must stay
-    // below 2^50 in the fixed-point units of the current (scale 2^32 or 2^40)
+    // One particle's current contribution is at most cmax = w / (dA dt) (plus
+    // w / (dz dx) for the 2D out-of-plane current).  FP64 path: scale 2^40,
+    // contributions below 2^50.  Split precision: each contribution is
+    // rounded to a 32-bit integer, so the scale is the largest power of two
+    // with cmax * scale <= 2^30, at most 2^32 and at least 2^8.
     const double dA = p->dims == 3 ? std::min(p->dx * p->dy, std::min(p->dz * p->dy, p->dz * p->dx))
                                    : std::min(p->dx, p->dz);
     const double cmax = d.weight / (dA * d.dt) + d.weight / (p->dz * p->dx);
-    const double lim = p->precision == PIC_FP64 ? 1024.0 : 262144.0;
-    if (!(cmax < lim)) return fail(PIC_EINVAL, "current per particle %.3g exceeds the fixed-point range", cmax);
+    if (p->precision == PIC_FP64) {
+      if (!(cmax < 1024.0)) return fail(PIC_EINVAL, "current per particle %.3g exceeds the fixed-point range", cmax);
+      d.jscale = 1099511627776.0;
+    } else {
+      if (!(cmax <= 4194304.0)) return fail(PIC_EINVAL, "current per particle %.3g exceeds the fixed-point range", cmax);
+      int e = (int)std::floor(std::log2(1073741824.0 / cmax));
+      if (std::ldexp(cmax, e) > 1073741824.0) --e;
+      d.jscale = std::ldexp(1.0, std::min(e, 32));
+    }
   }
   d.rsz = p->precision == PIC_FP64 ? sizeof(double) : sizeof(float);
   return PIC_OK;
@@ -414,9 +425,8 @@ pic_status pic_init_boosted(const pic_lab_params* p, void* dev_buf, size_t bytes
   h.L_lab = d.L_lab;
   h.zc_boost = d.zc_boost;
   h.waist = r->p.waist;
-  // current in 64-bit fixed point: 2^-32 resolution for the split-precision
-  // path, 2^-40 for the FP64 path
-  h.jscale = r->p.precision == PIC_FP64 ? 1099511627776.0 : 4294967296.0;
+  // current in 64-bit fixed point (scale chosen in derive)
+  h.jscale = d.jscale;
   h.jinv = 1.0 / h.jscale;
   h.seed = r->p.seed;
   const Layout& L = r->L;

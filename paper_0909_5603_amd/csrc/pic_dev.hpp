@@ -9,6 +9,20 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+// Address spaces of the device pointers held in the run descriptor: global
+// for the arrays, constant for the read-only descriptors.  Typed pointers let
+// the compiler emit global and scalar loads instead of flat ones (a flat
+// access counts against both the memory and the LDS wait counters, so every
+// LDS wait would also wait for outstanding loads).  The host compilation
+// sees plain pointers of the same size and layout.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define PIC_G __attribute__((address_space(1)))
+#define PIC_C __attribute__((address_space(4)))
+#else
+#define PIC_G
+#define PIC_C
+#endif
+
 namespace pic {
 
 // ---------------------------------------------------------------- constants
@@ -83,26 +97,29 @@ struct RunDev {
   unsigned long long seed;
   // arrays (device addresses inside the caller's buffer); element type is
   // float (split-precision path) or double (FP64 path)
-  void* E[2][3];
-  void* B[2][3];  // B at half-integer time: B^{n-1/2} in B[fbuf]
-  void* J[2][3];  // int64 fixed point; the step deposits into J[fbuf], the
-                  // field kernel reads it and clears J[fbuf^1] for the next step
-  int* cell[2];
-  void* off[2][3];
-  void* u[2][3];
-  unsigned* pid[2];
-  int* tile_start;  // ntiles + 1
-  int* tile_count;  // ntiles
-  int* tile_cursor; // ntiles
-  int* bbox[2];     // 6 ints per tile: lo z,x,y then hi z,x,y (tile-relative)
-  double* rho_a;
-  double* rho_b;
-  double* gauss0;
-  double* jlast[3];
-  int* cell_snap;
-  int* slowq;       // slots of particles deferred to the HBM path this step
-  Counters* ctr;
+  PIC_G void* E[2][3];
+  PIC_G void* B[2][3];  // B at half-integer time: B^{n-1/2} in B[fbuf]
+  PIC_G void* J[2][3];  // int64 fixed point; the step deposits into J[fbuf], the
+                        // field kernel reads it and clears J[fbuf^1] for the next step
+  PIC_G int* cell[2];
+  PIC_G void* off[2][3];
+  PIC_G void* u[2][3];
+  PIC_G unsigned* pid[2];
+  PIC_G int* tile_start;  // ntiles + 1
+  PIC_G int* tile_count;  // ntiles
+  PIC_G int* tile_cursor; // ntiles
+  PIC_G int* bbox[2];     // 6 ints per tile: lo z,x,y then hi z,x,y (tile-relative)
+  PIC_G double* rho_a;
+  PIC_G double* rho_b;
+  PIC_G double* gauss0;
+  PIC_G double* jlast[3];
+  PIC_G int* cell_snap;
+  PIC_G int* slowq;       // slots of particles deferred to the HBM path this step
+  PIC_G Counters* ctr;
 };
+
+// a run descriptor as the kernels see it (read-only, constant address space)
+using RunC = const PIC_C RunDev;
 
 // A set of runs advanced by the same launches.  Work items of every kernel
 // are enumerated run by run; pre_* are exclusive prefix sums of the per-run
@@ -111,7 +128,7 @@ struct BatchTable {
   int n;
   int pad;
   long long tiles, cellblk, partblk, injblk;
-  const RunDev* run[MAX_BATCH];
+  RunC* run[MAX_BATCH];
   long long pre_tiles[MAX_BATCH + 1];
   long long pre_cellblk[MAX_BATCH + 1];
   long long pre_partblk[MAX_BATCH + 1];
@@ -176,11 +193,11 @@ __device__ __forceinline__ int cell_pack(int k, int i, int j) {
 
 // number of valid z indices of a component (open z: nodes 0..nz, half
 // points 0..nz-1; periodic: nz)
-__device__ __forceinline__ int zcount(const RunDev& r, int comp) {
+__device__ __forceinline__ int zcount(RunC& r, int comp) {
   return r.open ? (stag(comp, 0) ? r.nz : r.nz + 1) : r.nz;
 }
 
-__device__ __forceinline__ long long gidx(const RunDev& r, int k, int i, int j) {
+__device__ __forceinline__ long long gidx(RunC& r, int k, int i, int j) {
   return ((long long)j * r.nx + i) * r.nzf + k;
 }
 
@@ -208,17 +225,43 @@ __device__ __forceinline__ long long to_fixed(double x, double scale) {
   return __double_as_longlong(fma(x, scale, magic)) - 0x4338000000000000LL;
 }
 
+// relaxed device-scope atomics on global memory
+template <typename T>
+__device__ __forceinline__ T g_add(PIC_G T* a, T v) {
+  return __hip_atomic_fetch_add(a, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ T g_min(PIC_G T* a, T v) {
+  return __hip_atomic_fetch_min(a, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ T g_max(PIC_G T* a, T v) {
+  return __hip_atomic_fetch_max(a, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ T g_or(PIC_G T* a, T v) {
+  return __hip_atomic_fetch_or(a, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // bit pattern max for non-negative doubles
-__device__ __forceinline__ void atomic_max_pos(unsigned long long* a, double v) {
-  atomicMax(a, (unsigned long long)__double_as_longlong(v));
+__device__ __forceinline__ void atomic_max_pos(PIC_G unsigned long long* a, double v) {
+  g_max(a, (unsigned long long)__double_as_longlong(v));
 }
 
 // the sort/injection of a step runs when the step is a multiple of the
 // cadence and has not been sorted yet
-__device__ __forceinline__ bool sort_due(const Counters& c, int every) {
+__device__ __forceinline__ bool sort_due(const PIC_G Counters& c, int every) {
   return (c.step % every) == 0 && c.step != c.last_sort;
 }
 
-template <typename R> __device__ __forceinline__ R* fptr(void* p) { return reinterpret_cast<R*>(p); }
+template <typename R> __device__ __forceinline__ PIC_G R* fptr(PIC_G void* p) { return (PIC_G R*)p; }
+
+// the three component arrays of a field (or current) buffer
+template <typename R>
+struct Arr3 {
+  PIC_G R* p[3];
+  __device__ __forceinline__ PIC_G R* operator[](int c) const { return p[c]; }
+};
+#define PIC_ARR3(R, a) (::pic::Arr3<R>{{(PIC_G R*)(a)[0], (PIC_G R*)(a)[1], (PIC_G R*)(a)[2]}})
 
 }  // namespace pic
