@@ -16,6 +16,8 @@ bounded sample on this host.
 from __future__ import annotations
 
 import argparse
+import csv
+import hashlib
 import json
 import os
 import sys
@@ -27,6 +29,16 @@ if ROOT not in sys.path:
 
 METRIC = "particle-steps/s (full PIC step) FP32 vs FP64 + p50/p99 batched-run latency"
 HBM_PEAK_GBS = 8000.0
+
+# Measured HBM traffic of the particle kernel (rocprofv3 FETCH_SIZE and
+# WRITE_SIZE, calibrated against a copy kernel of known size).  It is reported
+# only while the kernel sources still hash to the value recorded with it.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_particles_3d_fp32_512x256x256_traffic.txt")
+KERNEL_SOURCES = ["paper_0909_5603_amd/csrc/k_step.hip", "paper_0909_5603_amd/csrc/pusher.hpp",
+                  "paper_0909_5603_amd/csrc/pic_dev.hpp"]
+PARTICLE_KERNEL = "k_particles<3, float, 256, 0>"
+COPY_KERNEL = "k_copy_bench"
+COPY_BYTES = 1 << 30
 
 
 def log(msg: str):
@@ -69,7 +81,94 @@ def run_main(cfg, precision, steps, warmup, pic, torch):
     return run, out
 
 
-def kernel_roofline(run, pic, nsteps):
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def read_traffic(workload: str):
+    """HBM bytes per launch of the particle kernel from the committed counter
+    summary, or None if there is none or the kernel changed since."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    with open(TRAFFIC_FILE) as fh:
+        for line in fh:
+            line = line.strip()
+            if line and not line.startswith("#") and "=" in line:
+                k, v = line.split("=", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("source_sha256") != kernel_source_hash() or kv.get("workload") != workload:
+        return None
+    return float(kv["traffic_bytes_per_launch"])
+
+
+def _counter_means(path: str, counter: str):
+    """Mean counter value per dispatch of the particle and the copy kernel."""
+    vals = {PARTICLE_KERNEL: [], COPY_KERNEL: []}
+    with open(path) as fh:
+        for r in csv.DictReader(fh):
+            if r["Counter_Name"] != counter:
+                continue
+            for k in vals:
+                if k in r["Kernel_Name"]:
+                    vals[k].append(float(r["Counter_Value"]))
+    if not vals[PARTICLE_KERNEL] or not vals[COPY_KERNEL]:
+        raise SystemExit(f"{path}: no {counter} samples for both kernels")
+    return {k: sum(v) / len(v) for k, v in vals.items()}, {k: len(v) for k, v in vals.items()}
+
+
+def summarize_traffic(fetch_csv: str, write_csv: str, workload: str, commands: list):
+    """Writes the traffic summary from two rocprofv3 --pmc runs (FETCH_SIZE,
+    then WRITE_SIZE; KiB per dispatch), each scaled by the reading of the
+    same counter for the copy kernel (COPY_BYTES read and written)."""
+    f, nf = _counter_means(fetch_csv, "FETCH_SIZE")
+    w, nw = _counter_means(write_csv, "WRITE_SIZE")
+    kf = COPY_BYTES / (f[COPY_KERNEL] * 1024.0)  # true bytes per counted byte
+    kw = COPY_BYTES / (w[COPY_KERNEL] * 1024.0)
+    fetch_b = f[PARTICLE_KERNEL] * 1024.0 * kf
+    write_b = w[PARTICLE_KERNEL] * 1024.0 * kw
+    lines = [
+        f"# HBM traffic of {PARTICLE_KERNEL} ({workload})",
+        "# rocprofv3 --pmc FETCH_SIZE, then WRITE_SIZE (KiB per dispatch), one run each;",
+        f"# calibration: {COPY_KERNEL} reading and writing {COPY_BYTES} bytes in the same runs",
+        *[f"# command: {c}" for c in commands],
+        f"workload = {workload}",
+        f"source_sha256 = {kernel_source_hash()}",
+        f"dispatches_fetch = {nf[PARTICLE_KERNEL]}",
+        f"dispatches_write = {nw[PARTICLE_KERNEL]}",
+        f"fetch_kib_per_dispatch = {f[PARTICLE_KERNEL]:.1f}",
+        f"write_kib_per_dispatch = {w[PARTICLE_KERNEL]:.1f}",
+        f"copy_fetch_kib = {f[COPY_KERNEL]:.1f}",
+        f"copy_write_kib = {w[COPY_KERNEL]:.1f}",
+        f"fetch_scale = {kf:.4f}",
+        f"write_scale = {kw:.4f}",
+        f"fetch_bytes_per_launch = {fetch_b:.4e}",
+        f"write_bytes_per_launch = {write_b:.4e}",
+        f"traffic_bytes_per_launch = {fetch_b + write_b:.6e}",
+    ]
+    os.makedirs(os.path.dirname(TRAFFIC_FILE), exist_ok=True)
+    with open(TRAFFIC_FILE, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def copy_calibration(pic, torch, reps=3):
+    """Launches the plain copy kernel on COPY_BYTES (the counter reference)."""
+    a = torch.full((COPY_BYTES,), 1, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    s = torch.cuda.current_stream()
+    for _ in range(reps):
+        pic.pic_copy_bench(a.data_ptr(), b.data_ptr(), COPY_BYTES, s.cuda_stream)
+    torch.cuda.synchronize()
+    assert bool((b == 1).all())
+    del a, b
+
+
+def kernel_roofline(run, pic, nsteps, workload=None):
     ms = pic.pic_step_timed(run.handle, nsteps)
     slots, live = pic.pic_particle_count(run.handle)
     ncell = run.npts
@@ -77,8 +176,9 @@ def kernel_roofline(run, pic, nsteps):
     b = algorithmic_bytes(live, ncell, run.params.dims, rsz)
     ach = b["particle_kernel"] / (ms["particles"] * 1e-3) / 1e9
     achf = b["field_kernel"] / (ms["fields"] * 1e-3) / 1e9
+    traffic = read_traffic(workload) if (workload and rsz == 4 and run.params.dims == 3) else None
     return ms, {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": ach / HBM_PEAK_GBS, "traffic": None,
+                "frac": ach / HBM_PEAK_GBS, "traffic": traffic,
                 "kernel": "k_particles (gather+push+move+deposit)",
                 "algorithmic_bytes_per_launch": b["particle_kernel"],
                 "bytes_per_particle": b["per_particle"], "particles_per_launch": live,
@@ -131,11 +231,20 @@ def main():
     ap.add_argument("--timing-steps", type=int, default=20)
     ap.add_argument("--serve-requests", type=int, default=64)
     ap.add_argument("--profile", action="store_true",
-                    help="only the split-precision timed loop (for rocprofv3 runs)")
+                    help="only the split-precision timed loop and the copy calibration kernel "
+                         "(for rocprofv3 runs)")
+    ap.add_argument("--summarize-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write the particle kernel's traffic summary from two rocprofv3 --pmc "
+                         "counter_collection.csv files (FETCH_SIZE run, WRITE_SIZE run)")
+    ap.add_argument("--commands", nargs="*", default=[],
+                    help="with --summarize-traffic: the profiler command lines, recorded in the summary")
     args = ap.parse_args()
+    if args.summarize_traffic:
+        summarize_traffic(*args.summarize_traffic, workload=args.workload, commands=args.commands)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(see the sharding paragraph in DESIGN.md)", file=sys.stderr)
+        print("bench.py runs on one GPU only: there is no multi-GPU path "
+              f"(asked for --gpus {args.gpus})", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -160,7 +269,7 @@ def main():
         "particles_in_box": r32["n_box"], "cells": cfg["nz"] * cfg["nx"] * cfg["ny"],
         "parallelism": "single GPU",
     }
-    ms, roof = kernel_roofline(run, pic, args.timing_steps)
+    ms, roof = kernel_roofline(run, pic, args.timing_steps, args.workload)
     line["roofline"] = roof
     line["diag_fp32"] = r32["diag"]
     line["slow_path_fraction"] = r32["slow_path_fraction"]
@@ -170,6 +279,7 @@ def main():
     del run
     torch.cuda.empty_cache()
     if args.profile:
+        copy_calibration(pic, torch)
         print(json.dumps(line), flush=True)
         return
     if not args.no_fp64:

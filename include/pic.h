@@ -198,6 +198,12 @@ pic_status pic_push_bench(int precision, int pusher, int64_t n, int nsteps, doub
                           const double B[3], void* Ex, void* u, int32_t* cell, void* off,
                           void* hip_stream);
 
+/* Streaming copy of nbytes (a multiple of 16) from src to dst, both
+ * caller-owned, 16-byte aligned, non-overlapping device buffers: one kernel
+ * that reads and writes each byte once, the reference of known traffic for
+ * calibrating hardware memory counters.  Asynchronous on hip_stream. */
+pic_status pic_copy_bench(const void* src, void* dst, int64_t nbytes, void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

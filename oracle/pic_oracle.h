@@ -17,7 +17,8 @@
  *     Vay 2008), the Boris pusher as the control it replaces;
  *   - charge-conserving current deposition (Esirkepov 2001, linear shape);
  *   - the Yee field update with first-order Mur boundaries at the open z ends.
- * Where the paper is silent the readings are listed in the design doc.
+ * Where the paper is silent, the choice made is stated at the routine that
+ * makes it.
  *
  * Conventions: lengths in c/omega_p, times in 1/omega_p, c = eps0 = 1,
  * electron charge -1 and mass 1, laboratory plasma density 1.  Grid index

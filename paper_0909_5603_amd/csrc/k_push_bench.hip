@@ -22,7 +22,7 @@ __global__ __launch_bounds__(256) void k_push_bench(long long n, R dt, R bx, R b
       push_boris<R>(ux, uy, uz, ex, R(0), R(0), bx, by, bz, eps);
     else
       push_vay<R>(ux, uy, uz, ex, R(0), R(0), bx, by, bz, eps);
-    const R ig = R(1) / sqrt(R(1) + ux * ux + uy * uy + uz * uz);
+    const R ig = frsq(R(1) + ux * ux + uy * uy + uz * uz);
     const R v[3] = {ux * ig, uy * ig, uz * ig};
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
@@ -62,6 +62,23 @@ void launch_push_bench(int prec, int pusher, long long n, double dt, const doubl
     hipLaunchKernelGGL(k, dim3((unsigned)g), dim3(256), 0, s, n, (float)dt, (float)B[0], (float)B[1],
                        (float)B[2], (const float*)Ex, (float*)u, cell, (float*)off);
   }
+}
+
+// Plain streaming copy of n 16-byte words (read n*16 bytes, write n*16
+// bytes): the reference kernel of known traffic against which the memory
+// counters of the other kernels are calibrated.
+__global__ __launch_bounds__(256) void k_copy_bench(const uint4* __restrict__ src, uint4* __restrict__ dst,
+                                                    long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
+void launch_copy_bench(const void* src, void* dst, long long n16, hipStream_t s) {
+  long long g = (n16 + 255) / 256;
+  if (g > 256 * 64) g = 256 * 64;
+  if (g < 1) g = 1;
+  hipLaunchKernelGGL(k_copy_bench, dim3((unsigned)g), dim3(256), 0, s, (const uint4*)src, (uint4*)dst, n16);
 }
 
 }  // namespace pic

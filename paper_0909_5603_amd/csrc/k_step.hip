@@ -343,9 +343,8 @@ __device__ __forceinline__ bool advance(const PConst<R>& K, R* o, R& ux, R& uy, 
     push_boris<R>(ux, uy, uz, ex, ey, ez, bx, by, bz, K.eps);
   else
     push_vay<R>(ux, uy, uz, ex, ey, ez, bx, by, bz, K.eps);
-  const R g1 = sqrt(R(1) + ux * ux + uy * uy + uz * uz);
-  const bool bad = !(g1 < R(3.0e38));
-  const R ig = R(1) / g1;
+  const R ig = frsq(R(1) + ux * ux + uy * uy + uz * uz);
+  const bool bad = !(ig > R(0));  // 1 + u^2 infinite or NaN
   R on[3];
   on[0] = o[0] + K.cdz * uz * ig;
   on[1] = o[1] + K.cdx * ux * ig;
@@ -536,7 +535,13 @@ __global__ __launch_bounds__(BLOCK) void k_particles(const BatchTable* __restric
     PIC_G R* __restrict__ uyp = fptr<R>(rd.u[pb][1]);
     PIC_G R* __restrict__ uzp = fptr<R>(rd.u[pb][2]);
     const PConst<R> K = pconst<DIM, R>(rd);
-    const int gz = rd.gz, gx = rd.gx, gy = rd.gy;
+    // Window coordinates of a particle are its cell minus the window origin;
+    // a periodic correction is needed only where the window crosses the
+    // periodic boundary (uniform per tile).  Open z never wraps.
+    const bool wrapz = !open && (w0[0] < 0 || w0[0] + Wd[0] > nz);
+    const bool wrapx = w0[1] < 0 || w0[1] + Wd[1] > nx;
+    const bool wrapy = DIM == 3 && (w0[2] < 0 || w0[2] + Wd[2] > ny);
+    // bounding box of the new cells, in window coordinates
     int bmin0 = 1 << 20, bmin1 = 1 << 20, bmin2 = 1 << 20;
     int bmax0 = -(1 << 20), bmax1 = -(1 << 20), bmax2 = -(1 << 20);
     bool bad = false;
@@ -590,12 +595,14 @@ __global__ __launch_bounds__(BLOCK) void k_particles(const BatchTable* __restric
       }
       if (c < 0) continue;  // removed
       const int k = cell_k(c), i = cell_i(c), j = DIM == 3 ? cell_j(c) : 0;
-      const int rk = open ? k - t0[0] : relw(k, t0[0], nz, gz);
-      const int ri = relw(i, t0[1], nx, gx);
-      const int rj = DIM == 3 ? relw(j, t0[2], ny, gy) : 0;
-      const int wk = rk - lo[0] + 1, wi = ri - lo[1] + 1, wj = DIM == 3 ? rj - lo[2] + 1 : 0;
-      const bool fast = wk >= 1 && wk <= Wd[0] - 3 && wi >= 1 && wi <= Wd[1] - 3 &&
-                        (DIM == 2 || (wj >= 1 && wj <= Wd[2] - 3));
+      int wk = k - w0[0], wi = i - w0[1], wj = DIM == 3 ? j - w0[2] : 0;
+      if (wrapz) wk = wrap1(wk, nz);
+      if (wrapx) wi = wrap1(wi, nx);
+      if (wrapy) wj = wrap1(wj, ny);
+      // the stencil (old cell -1 .. +2) lies in the window: 1 <= w <= Wd - 3
+      const bool fast = (unsigned)(wk - 1) <= (unsigned)(Wd[0] - 4) &&
+                        (unsigned)(wi - 1) <= (unsigned)(Wd[1] - 4) &&
+                        (DIM == 2 || (unsigned)(wj - 1) <= (unsigned)(Wd[2] - 4));
       if (!fast) {
         const unsigned e = g_add(&rd.ctr->n_slowq, 1u);
         if (e < (unsigned long long)rd.capacity) rd.slowq[e] = (int)p;
@@ -622,14 +629,14 @@ __global__ __launch_bounds__(BLOCK) void k_particles(const BatchTable* __restric
       uyp[p] = uy;
       uzp[p] = uz;
       if (!dead) {
-        const int nk = rk + cr[0];
-        const int ni = ri + cr[1];
+        const int nk = wk + cr[0];
+        const int ni = wi + cr[1];
         bmin0 = min(bmin0, nk);
         bmax0 = max(bmax0, nk);
         bmin1 = min(bmin1, ni);
         bmax1 = max(bmax1, ni);
         if (DIM == 3) {
-          const int nj = rj + cr[2];
+          const int nj = wj + cr[2];
           bmin2 = min(bmin2, nj);
           bmax2 = max(bmax2, nj);
         }
@@ -660,6 +667,9 @@ __global__ __launch_bounds__(BLOCK) void k_particles(const BatchTable* __restric
       const int t = threadIdx.x;
       int v = sred[t][0];
       for (int q = 1; q < BLOCK / 64; ++q) v = t < 3 ? min(v, sred[t][q]) : max(v, sred[t][q]);
+      // window -> tile-relative coordinates (window origin = tile origin + lo - 1)
+      const int d = t < 3 ? t : t - 3;
+      if (v != (t < 3 ? (1 << 20) : -(1 << 20))) v += lo[d] - 1;
       if (DIM == 2 && (t == 2 || t == 5)) v = 0;
       bbw[t] = v;
     }

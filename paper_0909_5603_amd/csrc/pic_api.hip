@@ -779,4 +779,16 @@ pic_status pic_push_bench(int precision, int pusher, int64_t n, int nsteps, doub
   return PIC_OK;
 }
 
+pic_status pic_copy_bench(const void* src, void* dst, int64_t nbytes, void* hip_stream) {
+  if (nbytes < 0) return fail(PIC_EINVAL, "negative size");
+  if (nbytes % 16 != 0) return fail(PIC_EINVAL, "nbytes must be a multiple of 16");
+  if (nbytes == 0) return PIC_OK;
+  if (!src || !dst) return fail(PIC_EINVAL, "NULL buffer");
+  if ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) % 16 != 0)
+    return fail(PIC_EINVAL, "buffers must be 16-byte aligned");
+  launch_copy_bench(src, dst, (long long)(nbytes / 16), static_cast<hipStream_t>(hip_stream));
+  HIPCHK(hipGetLastError());
+  return PIC_OK;
+}
+
 }  // extern "C"

@@ -21,11 +21,22 @@ namespace pic {
 #endif
 constexpr double GAMMA2_FP64 = PIC_GAMMA2_FP64;
 
+// Reciprocal, reciprocal square root and square root: one hardware
+// instruction each in FP32 (v_rcp_f32, v_rsq_f32, v_sqrt_f32, about 1 ulp
+// instead of the ~12-instruction correctly rounded sequences), IEEE in FP64.
+// Their arguments here are 1 + u^2, 1 + t^2 and positive sums: never
+// denormal.
+__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double frcp(double x) { return 1.0 / x; }
+__device__ __forceinline__ float frsq(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double frsq(double x) { return 1.0 / sqrt(x); }
+__device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double fsqrt(double x) { return sqrt(x); }
+
 template <typename R>
 __device__ __forceinline__ void push_vay(R& ux, R& uy, R& uz, R ex, R ey, R ez, R bx, R by, R bz,
                                          R eps) {
-  const R g = sqrt(R(1) + ux * ux + uy * uy + uz * uz);
-  const R ig = R(1) / g;
+  const R ig = frsq(R(1) + ux * ux + uy * uy + uz * uz);
   const R vx = ux * ig, vy = uy * ig, vz = uz * ig;
   // half electric kick plus magnetic force with the old velocity, then the
   // second electric half kick: u' = u + eps (2E + v x B)
@@ -51,18 +62,15 @@ __device__ __forceinline__ void push_vay(R& ux, R& uy, R& uz, R ex, R ey, R ez, 
     const double g2 = sigma >= 0.0 ? 0.5 * (sigma + disc) : 0.5 * a4 / (disc - sigma);
     // gamma_new^2 carries the FP64 accuracy; its reciprocal square root is
     // taken in R (for FP32 one v_rsq_f32, relative error ~1e-7)
-    if constexpr (sizeof(R) == 4)
-      ign = rsqrtf((float)g2);
-    else
-      ign = R(1.0 / sqrt(g2));
+    ign = R(frsq(R(g2)));
   } else {
     const R ustar = upx * tx + upy * ty + upz * tz;
     const R tau2 = tx * tx + ty * ty + tz * tz;
     const R sigma = R(1) + up2 - tau2;
     const R a4 = R(4) * (tau2 + ustar * ustar);
-    const R disc = sqrt(sigma * sigma + a4);
-    const R g2 = sigma >= R(0) ? R(0.5) * (sigma + disc) : R(0.5) * a4 / (disc - sigma);
-    ign = rsqrtf(g2);
+    const R disc = fsqrt(sigma * sigma + a4);
+    const R g2 = sigma >= R(0) ? R(0.5) * (sigma + disc) : R(0.5) * a4 * frcp(disc - sigma);
+    ign = frsq(g2);
   }
   // u_new = s (u' + (u'.t) t + u' x t),  t = tau / gamma_new,  s = 1/(1+t^2),
   // evaluated as u' + s ((u'.t) t + u' x t - t^2 u'): the small rotation is
@@ -70,7 +78,7 @@ __device__ __forceinline__ void push_vay(R& ux, R& uy, R& uz, R ex, R ey, R ez, 
   // rounded once per step instead of being scaled by s
   const R ttx = tx * ign, tty = ty * ign, ttz = tz * ign;
   const R t2 = ttx * ttx + tty * tty + ttz * ttz;
-  const R s = R(1) / (R(1) + t2);
+  const R s = frcp(R(1) + t2);
   const R upt = upx * ttx + upy * tty + upz * ttz;
   ux = upx + s * (upt * ttx + (upy * ttz - upz * tty) - t2 * upx);
   uy = upy + s * (upt * tty + (upz * ttx - upx * ttz) - t2 * upy);
@@ -81,12 +89,12 @@ template <typename R>
 __device__ __forceinline__ void push_boris(R& ux, R& uy, R& uz, R ex, R ey, R ez, R bx, R by,
                                            R bz, R eps) {
   const R mx = ux + eps * ex, my = uy + eps * ey, mz = uz + eps * ez;
-  const R ig = R(1) / sqrt(R(1) + mx * mx + my * my + mz * mz);
+  const R ig = frsq(R(1) + mx * mx + my * my + mz * mz);
   const R tx = eps * bx * ig, ty = eps * by * ig, tz = eps * bz * ig;
   const R px = mx + (my * tz - mz * ty);
   const R py = my + (mz * tx - mx * tz);
   const R pz = mz + (mx * ty - my * tx);
-  const R f = R(2) / (R(1) + tx * tx + ty * ty + tz * tz);
+  const R f = R(2) * frcp(R(1) + tx * tx + ty * ty + tz * tz);
   const R sx = f * tx, sy = f * ty, sz = f * tz;
   ux = mx + (py * sz - pz * sy) + eps * ex;
   uy = my + (pz * sx - px * sz) + eps * ey;

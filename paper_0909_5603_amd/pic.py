@@ -66,7 +66,7 @@ class pic_derived(ctypes.Structure):
 # names declared in include/pic.h, in order
 EXPORTS = ["pic_state_bytes", "pic_init_boosted", "pic_step", "pic_step_timed", "pic_step_batch", "pic_diag",
            "pic_particle_count", "pic_read_particles", "pic_read_fields", "pic_get_derived",
-           "pic_set_option", "pic_free", "pic_last_error", "pic_push_bench"]
+           "pic_set_option", "pic_free", "pic_last_error", "pic_push_bench", "pic_copy_bench"]
 
 _lib = None
 
@@ -96,6 +96,8 @@ def lib():
     L.pic_free.argtypes = [vp]
     L.pic_last_error.argtypes = []
     L.pic_last_error.restype = ctypes.c_char_p
+    L.pic_copy_bench.argtypes = [ctypes.c_void_p, ctypes.c_void_p, i64, ctypes.c_void_p]
+    L.pic_copy_bench.restype = ctypes.c_int
     L.pic_push_bench.argtypes = [ctypes.c_int, ctypes.c_int, i64, ctypes.c_int, ctypes.c_double, dp,
                                  vp, vp, vp, vp, vp]
     for n in EXPORTS:
@@ -222,6 +224,11 @@ def pic_push_bench(precision: int, pusher: int, n: int, nsteps: int, dt: float, 
     _check(lib().pic_push_bench(int(precision), int(pusher), int(n), int(nsteps), float(dt), b,
                                 ctypes.c_void_p(Ex_ptr), ctypes.c_void_p(u_ptr),
                                 ctypes.c_void_p(cell_ptr), ctypes.c_void_p(off_ptr),
+                                ctypes.c_void_p(stream)))
+
+
+def pic_copy_bench(src_ptr: int, dst_ptr: int, nbytes: int, stream: int):
+    _check(lib().pic_copy_bench(ctypes.c_void_p(src_ptr), ctypes.c_void_p(dst_ptr), int(nbytes),
                                 ctypes.c_void_p(stream)))
 
 

@@ -70,3 +70,12 @@ def test_null_arguments(pic):
     out = ctypes.c_void_p()
     p = pic.make_params(workloads.config("c1"))
     assert L.pic_init_boosted(ctypes.byref(p), None, 0, None, ctypes.byref(out)) == -1
+
+
+def test_copy_bench_rejects_bad_sizes_before_any_launch(pic):
+    L = pic.lib()
+    assert L.pic_copy_bench(None, None, 0, None) == 0  # empty copy: nothing to do
+    assert L.pic_copy_bench(None, None, -16, None) == -1
+    assert L.pic_copy_bench(None, None, 24, None) == -1  # not a multiple of 16
+    assert L.pic_copy_bench(None, None, 32, None) == -1  # NULL buffers
+    assert L.pic_copy_bench(8, 40, 32, None) == -1  # misaligned addresses: rejected before a launch
