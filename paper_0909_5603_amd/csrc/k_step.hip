@@ -379,8 +379,35 @@ __device__ __forceinline__ int new_cell(RunC& rd, int k, int i, int j, const int
   return cell_pack(k1, i1, j1) | (dead ? (int)DEAD : 0);
 }
 
+// Occupancy of the 3D particle kernel.  Its LDS window (about 77 KiB in
+// split precision, 115 KiB in FP64) admits two workgroups per CU (one in
+// FP64), so the workgroup is 512 threads and the registers are capped at
+// 512 / waves-per-SIMD: 16 resident waves per CU in split precision, 8 in
+// FP64.
+#ifndef PIC_PBLOCK3
+#define PIC_PBLOCK3 512
+#endif
+#ifndef PIC_WPE3
+#define PIC_WPE3 4
+#endif
+#ifndef PIC_PBLOCK3D
+#define PIC_PBLOCK3D 512
+#endif
+#ifndef PIC_WPE3D
+#define PIC_WPE3D 2
+#endif
+template <int DIM, typename R>
+struct PBlock {
+  static constexpr int value = DIM == 3 ? (sizeof(R) == 4 ? PIC_PBLOCK3 : PIC_PBLOCK3D) : 256;
+};
+template <int DIM, typename R, int BLOCK>
+struct PWaves {
+  static constexpr int value = DIM == 3 ? (sizeof(R) == 4 ? PIC_WPE3 : PIC_WPE3D) : 1;
+};
+
 template <int DIM, typename R, int BLOCK, int PUSHER>
-__global__ __launch_bounds__(BLOCK) void k_particles(const BatchTable* __restrict__ bt) {
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(PWaves<DIM, R, BLOCK>::value)))
+void k_particles(const BatchTable* __restrict__ bt) {
   using T = Tile<DIM>;
   constexpr int WZM = T::WZ, WXM = T::WX, WYM = T::WY;
   constexpr int WV = WZM * WXM * WYM;
@@ -941,14 +968,6 @@ __global__ void k_advance(const BatchTable* __restrict__ bt) {
 }
 
 // ------------------------------------------------------------------ launch
-// workgroup size of the particle kernel (3D split-precision path)
-#ifndef PIC_PBLOCK3
-#define PIC_PBLOCK3 256
-#endif
-template <int DIM, typename R>
-struct PBlock {
-  static constexpr int value = (DIM == 3 && sizeof(R) == 4) ? PIC_PBLOCK3 : 256;
-};
 
 int grid_particles(int dims, int prec, int ncu) {
   const size_t per_cell = 6 * sizeof(float) * (prec ? 2 : 1) + 3 * sizeof(long long);

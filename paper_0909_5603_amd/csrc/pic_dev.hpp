@@ -41,10 +41,16 @@ constexpr unsigned DEAD = 0x80000000u;
 // and two above (gather and deposit stencils): W = extent + 3, plus one cell
 // of slack for the fractional drift of the plasma between two sorts in z.
 template <int DIM> struct Tile;
+#ifndef PIC_WZ3
+#define PIC_WZ3 14
+#endif
+#ifndef PIC_WY3
+#define PIC_WY3 9
+#endif
 template <> struct Tile<3> {
   static constexpr int LZ = 3, LX = 3, LY = 2;
   static constexpr int TZ = 1 << LZ, TX = 1 << LX, TY = 1 << LY;
-  static constexpr int WZ = TZ + 6, WX = TX + 5, WY = TY + 5;
+  static constexpr int WZ = PIC_WZ3, WX = TX + 5, WY = PIC_WY3;
 };
 template <> struct Tile<2> {
   static constexpr int LZ = 4, LX = 4, LY = 0;
