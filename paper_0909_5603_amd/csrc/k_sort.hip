@@ -44,22 +44,43 @@ __device__ __forceinline__ int tile_of(RunC& rd, int c) {
 }
 
 // wavefront-aggregated atomic add of 1 per active lane to base[key];
-// returns the lane's slot (old value + rank among equal keys)
+// returns the lane's slot (old value + rank among equal keys).  The key
+// groups are found with ballots first; then the leader of every group makes
+// its atomic in one instruction, so the wavefront waits for one round trip
+// whatever the number of distinct keys.
 __device__ __forceinline__ int wave_agg_add(PIC_G int* base, int key, bool active) {
   const int lane = threadIdx.x & 63;
   unsigned long long pend = __ballot(active);
-  int slot = 0;
+  unsigned long long mine = 0;
+  int lead = 0;
   while (pend) {
     const int leader = __ffsll((long long)pend) - 1;
     const int lkey = __shfl(key, leader);
     const unsigned long long m = __ballot(active && key == lkey);
-    int b = 0;
-    if (lane == leader) b = g_add(base + lkey, (int)__popcll(m));
-    b = __shfl(b, leader);
-    if ((m >> lane) & 1ull) slot = b + __popcll(m & ((1ull << lane) - 1ull));
+    if ((m >> lane) & 1ull) {
+      mine = m;
+      lead = leader;
+    }
     pend &= ~m;
   }
-  return slot;
+  int b = 0;
+  if (active && lane == lead) b = g_add(base + key, (int)__popcll(mine));
+  b = __shfl(b, lead);
+  return b + (int)__popcll(mine & ((1ull << lane) - 1ull));
+}
+
+// the same count without the slots: one non-returning atomic per distinct
+// key of the wavefront
+__device__ __forceinline__ void wave_agg_count(PIC_G int* base, int key, bool active) {
+  const int lane = threadIdx.x & 63;
+  unsigned long long pend = __ballot(active);
+  while (pend) {
+    const int leader = __ffsll((long long)pend) - 1;
+    const int lkey = __shfl(key, leader);
+    const unsigned long long m = __ballot(active && key == lkey);
+    if (lane == leader) (void)g_add(base + lkey, (int)__popcll(m));
+    pend &= ~m;
+  }
 }
 
 // ------------------------------------------------------------------ inject
@@ -151,14 +172,14 @@ __global__ __launch_bounds__(256) void k_count(const BatchTable* __restrict__ bt
     if (total > rd.capacity) total = rd.capacity;
     const long long blk = w - bt->pre_partblk[r];
     if (blk * PART_CHUNK >= total) continue;
-    const int* cellp = rd.cell[c.pbuf];
+    const PIC_G int* cellp = rd.cell[c.pbuf];
     for (int t = threadIdx.x; t < PART_CHUNK; t += 256) {
       const long long q = blk * PART_CHUNK + t;
       int cc = -1;
       if (q < total) cc = cellp[q];
       const bool act = cc >= 0;
       const int key = act ? tile_of<DIM>(rd, cc) : 0;
-      wave_agg_add(rd.tile_count, key, act);
+      wave_agg_count(rd.tile_count, key, act);
     }
   }
 }
@@ -232,23 +253,36 @@ __global__ __launch_bounds__(256) void k_scatter(const BatchTable* __restrict__ 
     const long long blk = w - bt->pre_partblk[r];
     if (blk * PART_CHUNK >= total) continue;
     const int src = c.pbuf, dst = src ^ 1;
-    const int* cellp = rd.cell[src];
+    const PIC_G int* cellp = rd.cell[src];
     for (int t = threadIdx.x; t < PART_CHUNK; t += 256) {
       const long long q = blk * PART_CHUNK + t;
       int cc = -1;
       if (q < total) cc = cellp[q];
       const bool act = cc >= 0;
+      // the payload is loaded before the slot is known, so its latency
+      // overlaps the cursor atomic's
+      R v[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
+      unsigned id = 0;
+      if (act) {
+        v[0] = fptr<R>(rd.off[src][0])[q];
+        v[1] = fptr<R>(rd.off[src][1])[q];
+        if (DIM == 3) v[2] = fptr<R>(rd.off[src][2])[q];
+        v[3] = fptr<R>(rd.u[src][0])[q];
+        v[4] = fptr<R>(rd.u[src][1])[q];
+        v[5] = fptr<R>(rd.u[src][2])[q];
+        id = rd.pid[src][q];
+      }
       const int key = act ? tile_of<DIM>(rd, cc) : 0;
       const int slot = wave_agg_add(rd.tile_cursor, key, act);
       if (act) {
         rd.cell[dst][slot] = cc;
-        fptr<R>(rd.off[dst][0])[slot] = fptr<R>(rd.off[src][0])[q];
-        fptr<R>(rd.off[dst][1])[slot] = fptr<R>(rd.off[src][1])[q];
-        if (DIM == 3) fptr<R>(rd.off[dst][2])[slot] = fptr<R>(rd.off[src][2])[q];
-        fptr<R>(rd.u[dst][0])[slot] = fptr<R>(rd.u[src][0])[q];
-        fptr<R>(rd.u[dst][1])[slot] = fptr<R>(rd.u[src][1])[q];
-        fptr<R>(rd.u[dst][2])[slot] = fptr<R>(rd.u[src][2])[q];
-        rd.pid[dst][slot] = rd.pid[src][q];
+        fptr<R>(rd.off[dst][0])[slot] = v[0];
+        fptr<R>(rd.off[dst][1])[slot] = v[1];
+        if (DIM == 3) fptr<R>(rd.off[dst][2])[slot] = v[2];
+        fptr<R>(rd.u[dst][0])[slot] = v[3];
+        fptr<R>(rd.u[dst][1])[slot] = v[4];
+        fptr<R>(rd.u[dst][2])[slot] = v[5];
+        rd.pid[dst][slot] = id;
       }
     }
   }

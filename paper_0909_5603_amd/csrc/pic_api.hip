@@ -211,9 +211,15 @@ struct pic_run {
   BatchTable htabB;
   int ncu, gpart, ggen;
   bool use_graph;
-  hipGraphExec_t g1;   // one single-run step
-  hipGraphExec_t gB;   // one batched step (this run's batch table)
+  hipGraphExec_t g1;   // one single-run step with the sort chain
+  hipGraphExec_t g1n;  // one single-run step without it
+  hipGraphExec_t gB;   // one batched step (this run's batch table), with the sort chain
+  hipGraphExec_t gBn;  // the same without it
   unsigned gB_flags;
+  // host mirror of the device step counter and of the step of the last
+  // sort: the sort chain is enqueued only on steps where it has work (the
+  // device decides again from its own counters, so the two must agree)
+  long long hstep, hlast_sort;
 };
 
 namespace {
@@ -245,11 +251,22 @@ void fill_table(BatchTable& t, pic_run* const* runs, int n) {
   t.pre_injblk[n] = t.injblk = e;
 }
 
+// does the next step of run r sort (and inject)?  Same rule as the device:
+// a multiple of the cadence that has not been sorted yet
+bool host_sort_due(const pic_run* r) {
+  return r->hstep % r->p.sort_every == 0 && r->hstep != r->hlast_sort;
+}
+
+void host_advance(pic_run* r) {
+  if (host_sort_due(r)) r->hlast_sort = r->hstep;
+  ++r->hstep;
+}
+
 // enqueue one step for the runs of a batch table
-void enqueue_step(pic_run* r0, const BatchTable* tab, bool cont) {
+void enqueue_step(pic_run* r0, const BatchTable* tab, bool cont, bool sort) {
   const int dims = r0->p.dims, prec = r0->p.precision;
   hipStream_t s = r0->stream;
-  launch_sort_chain(dims, prec, tab, MAX_BATCH, r0->ggen, s);
+  if (sort) launch_sort_chain(dims, prec, tab, MAX_BATCH, r0->ggen, s);
   if (cont) {
     launch_cont_pre(dims, prec, r0->drd, r0->d.npts, r0->d.capacity, s);
     launch_rho(dims, prec, r0->drd, at<double>(r0, r0->L.rho_a), r0->d.npts, r0->d.capacity, 1, s);
@@ -263,10 +280,10 @@ void enqueue_step(pic_run* r0, const BatchTable* tab, bool cont) {
   launch_advance(tab, MAX_BATCH, s);
 }
 
-pic_status capture(pic_run* r, const BatchTable* tab, bool cont, hipGraphExec_t* out) {
+pic_status capture(pic_run* r, const BatchTable* tab, bool cont, bool sort, hipGraphExec_t* out) {
   hipGraph_t g = nullptr;
   HIPCHK(hipStreamBeginCapture(r->stream, hipStreamCaptureModeThreadLocal));
-  enqueue_step(r, tab, cont);
+  enqueue_step(r, tab, cont, sort);
   hipError_t e = hipStreamEndCapture(r->stream, &g);
   if (e != hipSuccess) return fail(PIC_EHIP, "graph capture: %s", hipGetErrorString(e));
   e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
@@ -278,6 +295,9 @@ pic_status capture(pic_run* r, const BatchTable* tab, bool cont, hipGraphExec_t*
 pic_status read_counters(pic_run* r, Counters& c) {
   HIPCHK(hipMemcpyAsync(&c, r->dctr, sizeof(Counters), hipMemcpyDeviceToHost, r->stream));
   HIPCHK(hipStreamSynchronize(r->stream));
+  if (c.step != r->hstep || c.last_sort != r->hlast_sort)
+    return fail(PIC_ESTATE, "step counters disagree (device step %lld sort %lld, host %lld %lld)", c.step,
+                c.last_sort, r->hstep, r->hlast_sort);
   return PIC_OK;
 }
 
@@ -373,7 +393,12 @@ pic_status pic_init_boosted(const pic_lab_params* p, void* dev_buf, size_t bytes
   r->stream = static_cast<hipStream_t>(hip_stream);
   r->use_graph = true;
   r->g1 = nullptr;
+  r->g1n = nullptr;
   r->gB = nullptr;
+  r->gBn = nullptr;
+  // the initial sort below runs at step 0
+  r->hstep = 0;
+  r->hlast_sort = 0;
   int dev = 0;
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&r->ncu, hipDeviceAttributeMultiprocessorCount, dev);
@@ -510,14 +535,20 @@ pic_status pic_step(pic_run* r, int nsteps) {
   if (nsteps < 0) return fail(PIC_EINVAL, "nsteps < 0");
   const bool cont = (r->p.diag_flags & PIC_DIAGF_CONTINUITY) != 0;
   // the legacy null stream cannot be captured: launch eagerly there
-  if (r->use_graph && r->stream != nullptr && nsteps >= 2) {
-    if (!r->g1) {
-      pic_status s = capture(r, r->dtab1, cont, &r->g1);
-      if (s != PIC_OK) return s;
+  const bool graph = r->use_graph && r->stream != nullptr && nsteps >= 2;
+  for (int i = 0; i < nsteps; ++i) {
+    const bool sort = host_sort_due(r);
+    if (graph) {
+      hipGraphExec_t& g = sort ? r->g1 : r->g1n;
+      if (!g) {
+        pic_status st = capture(r, r->dtab1, cont, sort, &g);
+        if (st != PIC_OK) return st;
+      }
+      HIPCHK(hipGraphLaunch(g, r->stream));
+    } else {
+      enqueue_step(r, r->dtab1, cont, sort);
     }
-    for (int i = 0; i < nsteps; ++i) HIPCHK(hipGraphLaunch(r->g1, r->stream));
-  } else {
-    for (int i = 0; i < nsteps; ++i) enqueue_step(r, r->dtab1, cont);
+    host_advance(r);
   }
   HIPCHK(hipGetLastError());
   return PIC_OK;
@@ -542,7 +573,8 @@ pic_status pic_step_timed(pic_run* r, int nsteps, double ms[4]) {
     for (int i = 0; i < nsteps; ++i) {
       hipEvent_t* e = &ev[(size_t)i * 4];
       (void)hipEventRecord(e[0], s);
-      launch_sort_chain(dims, prec, r->dtab1, MAX_BATCH, r->ggen, s);
+      if (host_sort_due(r)) launch_sort_chain(dims, prec, r->dtab1, MAX_BATCH, r->ggen, s);
+      host_advance(r);
       (void)hipEventRecord(e[1], s);
       launch_particles(dims, prec, r->p.pusher, r->dtab1, r->gpart, s);
       (void)hipEventRecord(e[2], s);
@@ -601,15 +633,19 @@ pic_status pic_step_batch(pic_run* const* runs, const int* nsteps, int n) {
       HIPCHK(hipMemcpyAsync(r0->dtabB, &r0->htabB, sizeof(BatchTable), hipMemcpyHostToDevice,
                             r0->stream));
     }
+    bool sort = false;
+    for (pic_run* q : act) sort = sort || host_sort_due(q);
     if (r0->use_graph && r0->stream != nullptr) {
-      if (!r0->gB) {
-        pic_status st = capture(r0, r0->dtabB, false, &r0->gB);
+      hipGraphExec_t& g = sort ? r0->gB : r0->gBn;
+      if (!g) {
+        pic_status st = capture(r0, r0->dtabB, false, sort, &g);
         if (st != PIC_OK) return st;
       }
-      HIPCHK(hipGraphLaunch(r0->gB, r0->stream));
+      HIPCHK(hipGraphLaunch(g, r0->stream));
     } else {
-      enqueue_step(r0, r0->dtabB, false);
+      enqueue_step(r0, r0->dtabB, false, sort);
     }
+    for (pic_run* q : act) host_advance(q);
   }
   HIPCHK(hipGetLastError());
   return PIC_OK;
@@ -758,7 +794,9 @@ pic_status pic_get_derived(const pic_run* r, pic_derived* o) {
 pic_status pic_free(pic_run* r) {
   if (!r) return PIC_OK;
   if (r->g1) (void)hipGraphExecDestroy(r->g1);
+  if (r->g1n) (void)hipGraphExecDestroy(r->g1n);
   if (r->gB) (void)hipGraphExecDestroy(r->gB);
+  if (r->gBn) (void)hipGraphExecDestroy(r->gBn);
   delete r;
   return PIC_OK;
 }
