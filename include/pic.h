@@ -50,8 +50,9 @@ enum { PIC_BC_OPEN = 0, PIC_BC_PERIODIC = 1 };
 enum { PIC_VAY = 0, PIC_BORIS = 1 };
 enum { PIC_FP32_SPLIT = 0, PIC_FP64 = 1 };
 
-/* device error-word bits */
-enum { PIC_ERR_NAN = 1u, PIC_ERR_CAPACITY = 2u, PIC_ERR_CELL = 4u };
+/* device error-word bits: a non-finite momentum; particle storage full; a
+ * tile holding 2^28 or more particles (its particles are then not advanced) */
+enum { PIC_ERR_NAN = 1u, PIC_ERR_CAPACITY = 2u, PIC_ERR_TILE = 4u };
 
 /* pic_lab_params.diag_flags */
 enum {

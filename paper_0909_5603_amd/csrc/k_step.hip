@@ -368,14 +368,11 @@ __device__ __forceinline__ bool advance(const PConst<R>& K, R* o, R& ux, R& uy, 
 template <int DIM>
 __device__ __forceinline__ int new_cell(RunC& rd, int k, int i, int j, const int* cr, bool& dead,
                                         int& k1, int& i1, int& j1) {
-  k1 = k + cr[0];
-  i1 = wrap1(i + cr[1], rd.nx);
-  j1 = DIM == 3 ? wrap1(j + cr[2], rd.ny) : 0;
-  dead = false;
-  if (rd.open)
-    dead = k1 < 0 || k1 >= rd.ztop;
-  else
-    k1 = wrap1(k1, rd.nz);
+  const bool open = rd.open != 0;
+  k1 = wrapu(k + cr[0], open ? 0 : rd.nz);
+  i1 = wrapu(i + cr[1], rd.nx);
+  j1 = DIM == 3 ? wrapu(j + cr[2], rd.ny) : 0;
+  dead = open && (unsigned)k1 >= (unsigned)rd.ztop;  // left through z = 0 or beyond ztop
   return cell_pack(k1, i1, j1) | (dead ? (int)DEAD : 0);
 }
 
@@ -438,7 +435,7 @@ void k_particles(const BatchTable* __restrict__ bt) {
     const int tz = tile % ntz, rest = tile / ntz;
     const int tx = rest % ntx, ty = rest / ntx;
     const int t0[3] = {tz * T::TZ, tx * T::TX, ty * T::TY};
-    const long long p0 = rd.tile_start[tile], p1 = rd.tile_start[tile + 1];
+    const unsigned p0 = (unsigned)rd.tile_start[tile], p1 = (unsigned)rd.tile_start[tile + 1];
     PIC_G int* bbw = rd.bbox[bb ^ 1] + 6 * tile;
     if (p0 >= p1) {
       if (threadIdx.x == 0) {
@@ -554,20 +551,29 @@ void k_particles(const BatchTable* __restrict__ bt) {
 
     // ---- particles whose stencil lies in the window; the others are queued
     // for the HBM kernel
-    PIC_G int* __restrict__ cellp = rd.cell[pb];
-    PIC_G R* __restrict__ o0p = fptr<R>(rd.off[pb][0]);
-    PIC_G R* __restrict__ o1p = fptr<R>(rd.off[pb][1]);
-    PIC_G R* __restrict__ o2p = fptr<R>(rd.off[pb][2]);
-    PIC_G R* __restrict__ uxp = fptr<R>(rd.u[pb][0]);
-    PIC_G R* __restrict__ uyp = fptr<R>(rd.u[pb][1]);
-    PIC_G R* __restrict__ uzp = fptr<R>(rd.u[pb][2]);
+    // The seven particle arrays are addressed from bases advanced to the
+    // tile's first slot (scalar registers) plus one 32-bit byte offset per
+    // particle, shared by all of them.  A tile holds far fewer than 2^28
+    // particles; one that does not is flagged and left alone.
+    const unsigned nt = p1 - p0;
+    if (nt >= (1u << 28)) {
+      if (threadIdx.x == 0) g_or(&rd.ctr->err, (unsigned)PIC_ERR_TILE);
+      continue;
+    }
+    PIC_G int* __restrict__ cellp = rd.cell[pb] + p0;
+    PIC_G R* __restrict__ o0p = fptr<R>(rd.off[pb][0]) + p0;
+    PIC_G R* __restrict__ o1p = fptr<R>(rd.off[pb][1]) + p0;
+    PIC_G R* __restrict__ o2p = fptr<R>(rd.off[pb][2]) + p0;
+    PIC_G R* __restrict__ uxp = fptr<R>(rd.u[pb][0]) + p0;
+    PIC_G R* __restrict__ uyp = fptr<R>(rd.u[pb][1]) + p0;
+    PIC_G R* __restrict__ uzp = fptr<R>(rd.u[pb][2]) + p0;
     const PConst<R> K = pconst<DIM, R>(rd);
     // Window coordinates of a particle are its cell minus the window origin;
     // a periodic correction is needed only where the window crosses the
     // periodic boundary (uniform per tile).  Open z never wraps.
-    const bool wrapz = !open && (w0[0] < 0 || w0[0] + Wd[0] > nz);
-    const bool wrapx = w0[1] < 0 || w0[1] + Wd[1] > nx;
-    const bool wrapy = DIM == 3 && (w0[2] < 0 || w0[2] + Wd[2] > ny);
+    const int wrapz = (!open && (w0[0] < 0 || w0[0] + Wd[0] > nz)) ? nz : 0;
+    const int wrapx = (w0[1] < 0 || w0[1] + Wd[1] > nx) ? nx : 0;
+    const int wrapy = (DIM == 3 && (w0[2] < 0 || w0[2] + Wd[2] > ny)) ? ny : 0;
     // bounding box of the new cells, in window coordinates
     int bmin0 = 1 << 20, bmin1 = 1 << 20, bmin2 = 1 << 20;
     int bmax0 = -(1 << 20), bmax1 = -(1 << 20), bmax2 = -(1 << 20);
@@ -576,30 +582,31 @@ void k_particles(const BatchTable* __restrict__ bt) {
     // software pipeline: the state of the particles two iterations ahead is
     // loaded while the current one is advanced (occupancy is set by the LDS
     // window, so the extra registers are free)
-    long long p = p0 + threadIdx.x;
+    unsigned u = threadIdx.x;  // slot relative to the tile's first
     int cA = -1, cB = -1;
     R oA0 = R(0), oA1 = R(0), oA2 = R(0), uA0 = R(0), uA1 = R(0), uA2 = R(0);
     R oB0 = R(0), oB1 = R(0), oB2 = R(0), uB0 = R(0), uB1 = R(0), uB2 = R(0);
-    if (p < p1) {
-      cA = cellp[p];
-      oA0 = o0p[p];
-      oA1 = o1p[p];
-      if (DIM == 3) oA2 = o2p[p];
-      uA0 = uxp[p];
-      uA1 = uyp[p];
-      uA2 = uzp[p];
+    if (u < nt) {
+      const unsigned bi = u * 4u, br = u * (unsigned)sizeof(R);
+      cA = at32(cellp, bi);
+      oA0 = at32(o0p, br);
+      oA1 = at32(o1p, br);
+      if (DIM == 3) oA2 = at32(o2p, br);
+      uA0 = at32(uxp, br);
+      uA1 = at32(uyp, br);
+      uA2 = at32(uzp, br);
     }
-    if (p + BLOCK < p1) {
-      const long long q = p + BLOCK;
-      cB = cellp[q];
-      oB0 = o0p[q];
-      oB1 = o1p[q];
-      if (DIM == 3) oB2 = o2p[q];
-      uB0 = uxp[q];
-      uB1 = uyp[q];
-      uB2 = uzp[q];
+    if (u + BLOCK < nt) {
+      const unsigned bi = (u + BLOCK) * 4u, br = (u + BLOCK) * (unsigned)sizeof(R);
+      cB = at32(cellp, bi);
+      oB0 = at32(o0p, br);
+      oB1 = at32(o1p, br);
+      if (DIM == 3) oB2 = at32(o2p, br);
+      uB0 = at32(uxp, br);
+      uB1 = at32(uyp, br);
+      uB2 = at32(uzp, br);
     }
-    for (; p < p1; p += BLOCK) {
+    for (; u < nt; u += BLOCK) {
       const int c = cA;
       R o[3] = {oA0, oA1, oA2};
       R ux = uA0, uy = uA1, uz = uA2;
@@ -610,29 +617,30 @@ void k_particles(const BatchTable* __restrict__ bt) {
       uA0 = uB0;
       uA1 = uB1;
       uA2 = uB2;
-      const long long pn = p + 2 * BLOCK;
-      if (pn < p1) {
-        cB = cellp[pn];
-        oB0 = o0p[pn];
-        oB1 = o1p[pn];
-        if (DIM == 3) oB2 = o2p[pn];
-        uB0 = uxp[pn];
-        uB1 = uyp[pn];
-        uB2 = uzp[pn];
+      const unsigned un = u + 2 * BLOCK;
+      if (un < nt) {
+        const unsigned bi = un * 4u, br = un * (unsigned)sizeof(R);
+        cB = at32(cellp, bi);
+        oB0 = at32(o0p, br);
+        oB1 = at32(o1p, br);
+        if (DIM == 3) oB2 = at32(o2p, br);
+        uB0 = at32(uxp, br);
+        uB1 = at32(uyp, br);
+        uB2 = at32(uzp, br);
       }
       if (c < 0) continue;  // removed
       const int k = cell_k(c), i = cell_i(c), j = DIM == 3 ? cell_j(c) : 0;
       int wk = k - w0[0], wi = i - w0[1], wj = DIM == 3 ? j - w0[2] : 0;
-      if (wrapz) wk = wrap1(wk, nz);
-      if (wrapx) wi = wrap1(wi, nx);
-      if (wrapy) wj = wrap1(wj, ny);
+      wk = wrapu(wk, wrapz);
+      wi = wrapu(wi, wrapx);
+      if (DIM == 3) wj = wrapu(wj, wrapy);
       // the stencil (old cell -1 .. +2) lies in the window: 1 <= w <= Wd - 3
       const bool fast = (unsigned)(wk - 1) <= (unsigned)(Wd[0] - 4) &&
                         (unsigned)(wi - 1) <= (unsigned)(Wd[1] - 4) &&
                         (DIM == 2 || (unsigned)(wj - 1) <= (unsigned)(Wd[2] - 4));
       if (!fast) {
         const unsigned e = g_add(&rd.ctr->n_slowq, 1u);
-        if (e < (unsigned long long)rd.capacity) rd.slowq[e] = (int)p;
+        if (e < (unsigned long long)rd.capacity) rd.slowq[e] = (int)(p0 + u);
         continue;
       }
       const int base = (wj * WXM + wi) * WZM + wk;
@@ -648,13 +656,14 @@ void k_particles(const BatchTable* __restrict__ bt) {
           });
       bool dead;
       int k1, i1, j1;
-      cellp[p] = new_cell<DIM>(rd, k, i, j, cr, dead, k1, i1, j1);
-      o0p[p] = o[0];
-      o1p[p] = o[1];
-      if (DIM == 3) o2p[p] = o[2];
-      uxp[p] = ux;
-      uyp[p] = uy;
-      uzp[p] = uz;
+      const unsigned bi = u * 4u, br = u * (unsigned)sizeof(R);
+      at32(cellp, bi) = new_cell<DIM>(rd, k, i, j, cr, dead, k1, i1, j1);
+      at32(o0p, br) = o[0];
+      at32(o1p, br) = o[1];
+      if (DIM == 3) at32(o2p, br) = o[2];
+      at32(uxp, br) = ux;
+      at32(uyp, br) = uy;
+      at32(uzp, br) = uz;
       if (!dead) {
         const int nk = wk + cr[0];
         const int ni = wi + cr[1];
@@ -936,22 +945,23 @@ __global__ __launch_bounds__(256) void k_efull(const BatchTable* __restrict__ bt
 
 template <typename R>
 __global__ __launch_bounds__(256) void k_mur(const BatchTable* __restrict__ bt) {
-  const XcdSplit xs(bt->cellblk);
-  for (long long w = xs.beg; w < xs.end; w += xs.stride) {
-    const int r = __builtin_amdgcn_readfirstlane(locate(bt->pre_cellblk, bt->n, w));
+  // 2 nperp boundary columns per open run, visited run by run (a batch
+  // holds few runs, so the outer loop is short and uniform)
+  for (int r = 0; r < bt->n; ++r) {
     RunC& rd = *bt->run[r];
     if (!rd.open) continue;
-    const long long q = (w - bt->pre_cellblk[r]) * CELL_BLOCK + threadIdx.x;
-    if (q >= 2 * rd.nperp) continue;
-    const int side = (int)(q / rd.nperp);
-    const long long col = (q % rd.nperp) * rd.nzf;
+    const unsigned nperp = (unsigned)rd.nperp, nzf = (unsigned)rd.nzf;
     const int fb = rd.ctr->fbuf;
     const Arr3<R> E = PIC_ARR3(R, rd.E[fb]);
     const Arr3<R> En = PIC_ARR3(R, rd.E[fb ^ 1]);
     const R cm = R((rd.dt - rd.dz) / (rd.dt + rd.dz));
-    const int kb = side ? rd.nz : 0, ki = side ? rd.nz - 1 : 1;
-    for (int c = 0; c < 2; ++c)
-      En[c][col + kb] = E[c][col + ki] + cm * (En[c][col + ki] - E[c][col + kb]);
+    for (unsigned q = blockIdx.x * 256u + threadIdx.x; q < 2u * nperp; q += gridDim.x * 256u) {
+      const unsigned side = q >= nperp ? 1u : 0u;
+      const unsigned col = (q - side * nperp) * nzf;
+      const unsigned kb = side ? (unsigned)rd.nz : 0u, ki = side ? (unsigned)rd.nz - 1u : 1u;
+      for (int c = 0; c < 2; ++c)
+        En[c][col + kb] = E[c][col + ki] + cm * (En[c][col + ki] - E[c][col + kb]);
+    }
   }
 }
 

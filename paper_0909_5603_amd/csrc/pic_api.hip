@@ -690,6 +690,7 @@ pic_status pic_diag(pic_run* r, unsigned what, pic_diag_out* out) {
     HIPCHK(hipStreamSynchronize(s));
     if (c.err & PIC_ERR_NAN) return fail(PIC_ESTATE, "device error: non-finite momentum");
     if (c.err & PIC_ERR_CAPACITY) return fail(PIC_ESTATE, "device error: particle capacity exceeded");
+    if (c.err & PIC_ERR_TILE) return fail(PIC_ESTATE, "device error: a tile holds 2^28 or more particles");
     return fail(PIC_ESTATE, "device error word 0x%x", c.err);
   }
   HIPCHK(hipStreamSynchronize(s));

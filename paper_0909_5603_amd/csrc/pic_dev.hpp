@@ -9,6 +9,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "pic.h"
+
 // Address spaces of the device pointers held in the run descriptor: global
 // for the arrays, constant for the read-only descriptors.  Typed pointers let
 // the compiler emit global and scalar loads instead of flat ones (a flat
@@ -177,6 +179,13 @@ __device__ __forceinline__ int wrapi(int i, int n) {
 }
 // periodic wrap of an index in [-n, 2n) (one correction)
 __device__ __forceinline__ int wrap1(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+// periodic wrap of an index in (-n, 2n) with one three-way unsigned minimum:
+// of w, w + n and w - n exactly one lies in [0, n), and the others are >= n
+// as unsigned numbers.  n = 0 leaves w unchanged.
+__device__ __forceinline__ int wrapu(int w, int n) {
+  const unsigned a = (unsigned)w, b = (unsigned)(w + n), c = (unsigned)(w - n);
+  return (int)min(min(a, b), c);
+}
 // periodic wrap of an index in [-2n, 3n) (two corrections)
 __device__ __forceinline__ int wrap2(int i, int n) {
   i = i < 0 ? i + n : (i >= n ? i - n : i);
@@ -261,6 +270,13 @@ __device__ __forceinline__ bool sort_due(const PIC_G Counters& c, int every) {
 }
 
 template <typename R> __device__ __forceinline__ PIC_G R* fptr(PIC_G void* p) { return (PIC_G R*)p; }
+
+// element at byte offset b (32-bit, zero-extended) from a global base: the
+// base stays in scalar registers and the offset in one vector register
+template <typename T>
+__device__ __forceinline__ PIC_G T& at32(PIC_G T* base, unsigned b) {
+  return *(PIC_G T*)((PIC_G char*)base + b);
+}
 
 // the three component arrays of a field (or current) buffer
 template <typename R>

@@ -15,9 +15,9 @@
 
 namespace pic {
 
-// u'^2 above which the gamma solve runs in FP64 (gamma ~ 100)
+// u'^2 above which the gamma solve runs in FP64 (gamma ~ 1000)
 #ifndef PIC_GAMMA2_FP64
-#define PIC_GAMMA2_FP64 1.0e4
+#define PIC_GAMMA2_FP64 1.0e6
 #endif
 constexpr double GAMMA2_FP64 = PIC_GAMMA2_FP64;
 
@@ -46,10 +46,12 @@ __device__ __forceinline__ void push_vay(R& ux, R& uy, R& uz, R ex, R ey, R ez, 
   const R tx = eps * bx, ty = eps * by, tz = eps * bz;
   // gamma_new^2 = (sigma + sqrt(sigma^2 + 4 (tau^2 + u*^2))) / 2,
   // sigma = 1 + u'^2 - tau^2, u* = u'.tau.  At large gamma the "1 +" and the
-  // tau^2 terms of sigma drop below FP32 resolution, so the solve runs in FP64
-  // whenever some lane of the wavefront has u'^2 > GAMMA2_FP64 (gamma above
-  // ~100); below that FP32 keeps gamma_new to ~1e-8 relative.  The switch is
-  // wavefront-uniform, so no lane pays for both.
+  // tau^2 terms of sigma drop below FP32 resolution (the "1" is lost entirely
+  // above u'^2 ~ 2^24), so the solve runs in FP64 whenever some lane of the
+  // wavefront has u'^2 > GAMMA2_FP64 (gamma above ~1000, where the "1" is
+  // still 16 FP32 ulps of u'^2); below that the FP32 solve keeps gamma_new
+  // to ~1.3e-7 relative, the rounding level of the FP32 momentum itself.
+  // The switch is wavefront-uniform, so no lane pays for both.
   R ign;
   const R up2 = upx * upx + upy * upy + upz * upz;
   if (sizeof(R) == 8 || __any(up2 > R(GAMMA2_FP64))) {
