@@ -36,7 +36,7 @@ HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_particles_3d_fp32_512x256x256_traffic.txt")
 KERNEL_SOURCES = ["paper_0909_5603_amd/csrc/k_step.hip", "paper_0909_5603_amd/csrc/pusher.hpp",
                   "paper_0909_5603_amd/csrc/pic_dev.hpp"]
-PARTICLE_KERNEL = "k_particles<3, float, 256, 0>"
+PARTICLE_KERNEL = "k_particles<3, float,"
 COPY_KERNEL = "k_copy_bench"
 COPY_BYTES = 1 << 30
 
