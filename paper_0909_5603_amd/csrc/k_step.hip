@@ -105,21 +105,14 @@ __device__ __forceinline__ Dep1<R> dep1(R o0, R o1, int carry) {
 }
 
 // offset carry after a move of less than one cell (CFL)
+// (selects only: a branch per dimension costs more than the arithmetic)
 template <typename R>
 __device__ __forceinline__ int carry(R& o) {
-  if (o < R(0)) {
-    o += R(1);
-    if (o >= R(1)) {  // the sum rounded up to 1: stay in the cell at offset 0
-      o = R(0);
-      return 0;
-    }
-    return -1;
-  }
-  if (o >= R(1)) {
-    o -= R(1);
-    return 1;
-  }
-  return 0;
+  const int c = (int)(o >= R(1)) - (int)(o < R(0));
+  const R on = o - R(c);
+  const bool up1 = c < 0 && on >= R(1);  // o + 1 rounded up to 1: stay in the cell at offset 0
+  o = up1 ? R(0) : on;
+  return up1 ? 0 : c;
 }
 
 // A current contribution x, already in fixed-point units, as a 64-bit
@@ -138,27 +131,30 @@ __device__ __forceinline__ long long fixq(double x) { return to_fixed(x, 1.0); }
 // along the current's direction and F the time-averaged shape across it.
 // The coefficient c times the fixed-point scale is folded into P (cz, cx, cy
 // below), and add(comp, a, b, c, q) receives node offsets from the start of
-// the particle's 3-node window.  NXY = nodes visited across x and y: 3 when
-// some lane of the wavefront crossed a cell boundary in x or y, else 2 (the
-// third node and the second face then carry exact zeros).  Zero contributions are added like any other: a branch per
+// the particle's 3-node window.  NX, NY = nodes visited across x and y: 3
+// when some lane of the wavefront crossed a cell boundary in that dimension,
+// else 2 (the third node and the second face then carry exact zeros).  Zero contributions are added like any other: a branch per
 // contribution costs more than the LDS atomic it saves.
-template <typename R, int NXY, class A>
+template <typename R, int NX, int NY, class A>
 __device__ __forceinline__ void dep3(const Dep1<R>& Z, const Dep1<R>& X, const Dep1<R>& Y, R cz, R cx,
                                      R cy, A&& add) {
   R Ay[3], By[3], Ax[3], Bx[3];
 #pragma unroll
-  for (int c = 0; c < NXY; ++c) {
+  for (int c = 0; c < NY; ++c) {
     Ay[c] = Y.S0[c] + R(0.5) * Y.DS[c];
     By[c] = R(0.5) * Y.S0[c] + R(1.0 / 3.0) * Y.DS[c];
-    Ax[c] = X.S0[c] + R(0.5) * X.DS[c];
-    Bx[c] = R(0.5) * X.S0[c] + R(1.0 / 3.0) * X.DS[c];
+  }
+#pragma unroll
+  for (int b = 0; b < NX; ++b) {
+    Ax[b] = X.S0[b] + R(0.5) * X.DS[b];
+    Bx[b] = R(0.5) * X.S0[b] + R(1.0 / 3.0) * X.DS[b];
   }
   const R pz0 = Z.P[0] * cz, pz1 = Z.P[1] * cz;
   // J_z(face a; node b, c) = cz P_z[a] (S0x Ay + DSx By)
 #pragma unroll
-  for (int b = 0; b < NXY; ++b)
+  for (int b = 0; b < NX; ++b)
 #pragma unroll
-    for (int c = 0; c < NXY; ++c) {
+    for (int c = 0; c < NY; ++c) {
       const R f = X.S0[b] * Ay[c] + X.DS[b] * By[c];
       add(2, 0, b, c, fixq(pz0 * f));
       add(2, 1, b, c, fixq(pz1 * f));
@@ -166,26 +162,25 @@ __device__ __forceinline__ void dep3(const Dep1<R>& Z, const Dep1<R>& X, const D
   // J_x(node a; face b; node c) = cx P_x[b] (S0z Ay + DSz By)
   R px[2], py[2];
 #pragma unroll
-  for (int b = 0; b < NXY - 1; ++b) {
-    px[b] = X.P[b] * cx;
-    py[b] = Y.P[b] * cy;
-  }
+  for (int b = 0; b < NX - 1; ++b) px[b] = X.P[b] * cx;
+#pragma unroll
+  for (int c = 0; c < NY - 1; ++c) py[c] = Y.P[c] * cy;
 #pragma unroll
   for (int a = 0; a < 3; ++a)
 #pragma unroll
-    for (int c = 0; c < NXY; ++c) {
+    for (int c = 0; c < NY; ++c) {
       const R f = Z.S0[a] * Ay[c] + Z.DS[a] * By[c];
 #pragma unroll
-      for (int b = 0; b < NXY - 1; ++b) add(0, a, b, c, fixq(px[b] * f));
+      for (int b = 0; b < NX - 1; ++b) add(0, a, b, c, fixq(px[b] * f));
     }
   // J_y(node a, b; face c) = cy P_y[c] (S0z Ax + DSz Bx)
 #pragma unroll
   for (int a = 0; a < 3; ++a)
 #pragma unroll
-    for (int b = 0; b < NXY; ++b) {
+    for (int b = 0; b < NX; ++b) {
       const R f = Z.S0[a] * Ax[b] + Z.DS[a] * Bx[b];
 #pragma unroll
-      for (int c = 0; c < NXY - 1; ++c) add(1, a, b, c, fixq(py[c] * f));
+      for (int c = 0; c < NY - 1; ++c) add(1, a, b, c, fixq(py[c] * f));
     }
 }
 
@@ -225,12 +220,16 @@ __device__ __forceinline__ void dep2(const Dep1<R>& Z, const Dep1<R>& X, R cz, R
 
 template <int DIM, typename R, class A>
 __device__ __forceinline__ void deposit(const Dep1<R>* d, const int* cr, R cz, R cx, R cy, R cyv, A&& add) {
-  // wavefront-uniform: does any active lane cross a cell boundary in x or y?
+  // wavefront-uniform: does any active lane cross a cell boundary in x, in y?
   if constexpr (DIM == 3) {
-    if (__any(cr[1] != 0 || cr[2] != 0))
-      dep3<R, 3>(d[0], d[1], d[2], cz, cx, cy, add);
-    else
-      dep3<R, 2>(d[0], d[1], d[2], cz, cx, cy, add);
+    const bool ax = __any(cr[1] != 0), ay = __any(cr[2] != 0);
+    if (ax) {
+      if (ay) dep3<R, 3, 3>(d[0], d[1], d[2], cz, cx, cy, add);
+      else dep3<R, 3, 2>(d[0], d[1], d[2], cz, cx, cy, add);
+    } else {
+      if (ay) dep3<R, 2, 3>(d[0], d[1], d[2], cz, cx, cy, add);
+      else dep3<R, 2, 2>(d[0], d[1], d[2], cz, cx, cy, add);
+    }
   } else {
     if (__any(cr[1] != 0))
       dep2<R, 3>(d[0], d[1], cz, cx, cyv, add);
