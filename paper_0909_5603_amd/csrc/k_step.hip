@@ -98,8 +98,10 @@ __device__ __forceinline__ Dep1<R> dep1(R o0, R o1, int carry) {
   d.DS[0] = s10 - d.S0[0];
   d.DS[1] = s11 - d.S0[1];
   d.DS[2] = s12 - d.S0[2];
-  d.P[0] = up ? (o0 - R(1)) : dn ? a1 : (o0 - o1);
-  d.P[1] = up ? -o1 : dn ? o0 : R(0);
+  // P[0] = o0 - o1, o0 - 1 or 1 - o1 (stay, up, down) as one rounded
+  // difference; P[1] = -DS[2] = 0, -o1 or o0, exactly
+  d.P[0] = (dn ? R(1) : o0) - (up ? R(1) : o1);
+  d.P[1] = d.S0[2] - s12;
   d.base = dn ? -1 : 0;
   return d;
 }

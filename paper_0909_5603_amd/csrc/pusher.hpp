@@ -71,7 +71,10 @@ __device__ __forceinline__ void push_vay(R& ux, R& uy, R& uz, R ex, R ey, R ez, 
     const R sigma = R(1) + up2 - tau2;
     const R a4 = R(4) * (tau2 + ustar * ustar);
     const R disc = fsqrt(sigma * sigma + a4);
-    const R g2 = sigma >= R(0) ? R(0.5) * (sigma + disc) : R(0.5) * a4 * frcp(disc - sigma);
+    // both forms evaluated and selected (no divergent branch); the second
+    // avoids the cancellation when sigma < 0
+    const R g2p = R(0.5) * (sigma + disc), g2n = R(0.5) * a4 * frcp(disc - sigma);
+    const R g2 = sigma >= R(0) ? g2p : g2n;
     ign = frsq(g2);
   }
   // u_new = s (u' + (u'.t) t + u' x t),  t = tau / gamma_new,  s = 1/(1+t^2),
