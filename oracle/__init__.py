@@ -39,6 +39,7 @@ class Params(ctypes.Structure):
         ("a0", ctypes.c_double), ("lambda0_um", ctypes.c_double), ("waist", ctypes.c_double),
         ("tau_lab", ctypes.c_double), ("pol_axis", ctypes.c_int), ("bc_z", ctypes.c_int),
         ("pusher", ctypes.c_int), ("inject_every", ctypes.c_int), ("round_f32", ctypes.c_int),
+        ("filter_passes", ctypes.c_int), ("filter_compensate", ctypes.c_int),
     ]
 
 
@@ -94,6 +95,8 @@ def lib():
         L.ora_field_half_B.argtypes = [vp]
         L.ora_field_full_E.argtypes = [vp]
         L.ora_laser_lab.argtypes = [vp] + [ctypes.c_double] * 4 + [_D, _D]
+        L.ora_filter_current.argtypes = [vp]
+        L.ora_filter_nodes.argtypes = [vp, _D]
         L.ora_push_many.argtypes = [ctypes.c_int64, _D, _D, _D, _D, ctypes.c_double, ctypes.c_int, ctypes.c_int]
         _lib = L
     return _lib
@@ -162,6 +165,8 @@ def make_params(cfg: dict, round_f32: bool = False) -> Params:
     p.bc_z = BC_PERIODIC if cfg.get("bc_z", "open") == "periodic" else BC_OPEN
     p.pusher = BORIS if cfg.get("pusher", "vay") == "boris" else VAY
     p.inject_every = int(cfg.get("sort_every", 20)); p.round_f32 = 1 if round_f32 else 0
+    p.filter_passes = int(cfg.get("filter_passes", 0))
+    p.filter_compensate = int(cfg.get("filter_compensate", 0))
     return p
 
 
@@ -256,6 +261,14 @@ class State:
 
     def full_E(self):
         lib().ora_field_full_E(self._h)
+
+    def filter_current(self):
+        lib().ora_filter_current(self._h)
+
+    def filter_nodes(self, a: np.ndarray) -> np.ndarray:
+        out = np.ascontiguousarray(a, dtype=np.float64).reshape(-1).copy()
+        lib().ora_filter_nodes(self._h, _dp(out))
+        return out.reshape(self.shape)
 
     def laser_lab(self, z, t, x, y=0.0):
         E, B = np.zeros(3), np.zeros(3)

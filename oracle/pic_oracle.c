@@ -614,6 +614,66 @@ static void inject(ora_state* s, int64_t n) {
 }
 
 /* ------------------------------------------------------------------------ */
+/* Low-pass digital filter of the current (Sec. 2: the short-wavelength     */
+/* instability of boosted-frame runs is controlled with low-dispersion      */
+/* solvers and low-pass digital filtering; the paper gives no filter, the   */
+/* one here is the standard binomial one).  A pass along one axis replaces  */
+/* every value by wm a[q] + ws (a[q-1] + a[q+1]) on the component's own     */
+/* staggered grid: periodic axes wrap, along an open z axis the values      */
+/* outside the component's range count as zero.  N passes of (1/4,1/2,1/4)  */
+/* along each axis have the transfer function cos^2N(theta/2) per axis      */
+/* (theta = k * cell); the optional compensating pass (-N/4, 1+N/2, -N/4)   */
+/* multiplies it by 1 + N sin^2(theta/2), which restores the long-wave      */
+/* response to second order.                                                */
+static void filter_pass(const ora_state* s, double* a, int zcount, int axis, double ws, double wm) {
+  const int nx = s->p.nx, ny = s->p.ny;
+  const int periodic_z = s->p.bc_z == ORA_BC_PERIODIC;
+  double* t = (double*)malloc(sizeof(double) * s->npts);
+  memcpy(t, a, sizeof(double) * s->npts);
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i)
+      for (int k = 0; k < zcount; ++k) {
+        double lo, hi;
+        if (axis == 0) {
+          int km = k - 1, kp = k + 1;
+          if (periodic_z) {
+            km = wrapi(km, s->p.nz);
+            kp = wrapi(kp, s->p.nz);
+            lo = a[gidx(s, km, i, j)];
+            hi = a[gidx(s, kp, i, j)];
+          } else {
+            lo = km >= 0 ? a[gidx(s, km, i, j)] : 0.0;
+            hi = kp < zcount ? a[gidx(s, kp, i, j)] : 0.0;
+          }
+        } else if (axis == 1) {
+          lo = a[gidx(s, k, wrapi(i - 1, nx), j)];
+          hi = a[gidx(s, k, wrapi(i + 1, nx), j)];
+        } else {
+          lo = a[gidx(s, k, i, wrapi(j - 1, ny))];
+          hi = a[gidx(s, k, i, wrapi(j + 1, ny))];
+        }
+        t[gidx(s, k, i, j)] = wm * a[gidx(s, k, i, j)] + ws * (lo + hi);
+      }
+  memcpy(a, t, sizeof(double) * s->npts);
+  free(t);
+}
+
+static void filter_array(const ora_state* s, double* a, int zcount) {
+  const int naxes = s->p.dims == 3 ? 3 : 2;
+  const int N = s->p.filter_passes;
+  for (int n = 0; n < N; ++n)
+    for (int ax = 0; ax < naxes; ++ax) filter_pass(s, a, zcount, ax, 0.25, 0.5);
+  if (N > 0 && s->p.filter_compensate)
+    for (int ax = 0; ax < naxes; ++ax) filter_pass(s, a, zcount, ax, -0.25 * N, 1.0 + 0.5 * N);
+}
+
+void ora_filter_current(ora_state* s) {
+  for (int c = ORA_JX; c <= ORA_JZ; ++c) filter_array(s, s->F[c], zvalid_count(s, c));
+}
+
+void ora_filter_nodes(const ora_state* s, double* a) { filter_array(s, a, zvalid_count(s, ORA_EX)); }
+
+/* ------------------------------------------------------------------------ */
 /* diagnostics                                                              */
 static int interior_k(const ora_state* s, int comp, int k) {
   if (s->p.bc_z == ORA_BC_PERIODIC) return 1;
@@ -637,9 +697,13 @@ static void div_field(const ora_state* s, int cx, int cy, int cz, double* out) {
             (fval(s, cz, k, i, j) - fval(s, cz, k - 1, i, j)) * idz;
 }
 
+/* div E - rho - rho_ion on nodes.  With the current filter, E follows the
+ * filtered current, so the conserved quantity is div E - F(rho_e) - rho_ion
+ * (the filter commutes with the difference operators away from open ends). */
 static void gauss_field(const ora_state* s, double* G) {
   double* rho = (double*)malloc(sizeof(double) * s->npts);
   ora_rho(s, rho);
+  if (s->p.filter_passes > 0) ora_filter_nodes(s, rho);
   div_field(s, ORA_EX, ORA_EY, ORA_EZ, G);
   const double rho_ion = s->p.ppc > 0 ? s->d.gamma_b : 0.0;
   for (int64_t q = 0; q < s->npts; ++q) G[q] -= rho[q] + rho_ion;
@@ -840,6 +904,7 @@ void ora_step(ora_state* s, int nsteps, double* cont_max) {
       free(rho0);
       free(rho1);
     }
+    if (s->p.filter_passes > 0) ora_filter_current(s);
     ora_field_half_B(s);
     ora_field_full_E(s);
     ora_field_half_B(s);

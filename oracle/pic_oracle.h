@@ -57,6 +57,8 @@ typedef struct {
   int pusher;            /* ORA_VAY or ORA_BORIS */
   int inject_every;      /* plasma columns are created every this many steps */
   int round_f32;         /* round created offsets and momenta to FP32 */
+  int filter_passes;     /* passes of the 1-2-1 current filter per axis (0: none) */
+  int filter_compensate; /* 1: one compensating pass per axis after them */
 } ora_params;
 
 typedef struct {
@@ -119,6 +121,12 @@ void ora_deposit(ora_state* s, const double p0[3], const double p1[3], double vy
 void ora_rho(const ora_state* s, double* rho);        /* electron charge, nodes */
 void ora_field_half_B(ora_state* s);                  /* B -= dt/2 curl E */
 void ora_field_full_E(ora_state* s);                  /* E += dt (curl B - J) */
+/* low-pass filter of the current as configured (filter_passes,
+ * filter_compensate), applied by ora_step between the deposit and the field
+ * update; exposed for its pins */
+void ora_filter_current(ora_state* s);
+/* the same filter on a node-centred scalar array (rho), npts values */
+void ora_filter_nodes(const ora_state* s, double* a);
 void ora_laser_lab(const ora_state* s, double z, double t, double x, double y,
                    double E[3], double B[3]);
 
