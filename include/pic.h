@@ -82,6 +82,17 @@ typedef struct {
   int precision;         /* PIC_FP32_SPLIT or PIC_FP64 */
   int sort_every;        /* tile sort and plasma-column injection cadence (>= 1) */
   unsigned diag_flags;   /* PIC_DIAGF_* */
+  /* Low-pass digital filter of the current between the deposit and the field
+   * update (Sec. 2: the short-wavelength instability of boosted-frame runs
+   * is controlled with low-pass filtering): filter_passes (0..16) passes of
+   * the binomial stencil (1/4, 1/2, 1/4) along every axis on each
+   * component's own staggered grid, then, if filter_compensate = 1, one pass
+   * of (-N/4, 1 + N/2, -N/4) per axis.  Periodic axes wrap; along an open z
+   * axis values outside a component's range count as zero.  The continuity
+   * diagnostic uses the deposited current, the Gauss diagnostic the filtered
+   * electron density.  0 = no filter. */
+  int filter_passes;
+  int filter_compensate;
 } pic_lab_params;
 
 typedef struct pic_run pic_run; /* opaque host handle */

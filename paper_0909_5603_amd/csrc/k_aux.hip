@@ -290,11 +290,55 @@ __global__ void k_jlast(const RunDev* __restrict__ rdp) {
       rd.jlast[c][q] = (double)reinterpret_cast<const long long*>(rd.J[rd.ctr->fbuf][c])[q] * rd.jinv;
 }
 
+// ------------------------------------------------------------------ filter
+// One stage of the current filter applied to a node scalar (the electron
+// density of the filtered Gauss diagnostic): the same passes and weights as
+// the current's, with the z range of a node-type component.
+template <int DIM>
+__global__ __launch_bounds__(256) void k_filter_nodes(const RunDev* __restrict__ rdp, const double* src,
+                                                      double* dst, int stage) {
+  RunC& rd = *(RunC*)rdp;
+  constexpr int NAX = DIM == 3 ? 3 : 2;
+  const int axis = stage % NAX;
+  const bool cpass = stage >= rd.filter_passes * NAX;
+  const double ws = cpass ? -0.25 * rd.filter_passes : 0.25;
+  const double wm = cpass ? 1.0 + 0.5 * rd.filter_passes : 0.5;
+  const int zc = rd.open ? rd.nz + 1 : rd.nz;
+  for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < rd.npts;
+       q += (long long)gridDim.x * blockDim.x) {
+    const int k = (int)(q % rd.nzf);
+    const long long t = q / rd.nzf;
+    const int i = (int)(t % rd.nx), j = (int)(t / rd.nx);
+    if (k >= zc) {
+      dst[q] = 0.0;
+      continue;
+    }
+    double lo, hi;
+    if (axis == 0) {
+      if (rd.open) {
+        lo = k > 0 ? src[q - 1] : 0.0;
+        hi = k + 1 < zc ? src[q + 1] : 0.0;
+      } else {
+        lo = src[gidx(rd, wrapi(k - 1, rd.nz), i, j)];
+        hi = src[gidx(rd, wrapi(k + 1, rd.nz), i, j)];
+      }
+    } else if (axis == 1) {
+      lo = src[gidx(rd, k, wrapi(i - 1, rd.nx), j)];
+      hi = src[gidx(rd, k, wrapi(i + 1, rd.nx), j)];
+    } else {
+      lo = src[gidx(rd, k, i, wrapi(j - 1, rd.ny))];
+      hi = src[gidx(rd, k, i, wrapi(j + 1, rd.ny))];
+    }
+    dst[q] = wm * src[q] + ws * (lo + hi);
+  }
+}
+
 // ------------------------------------------------------------------ Gauss
-// mode 0: store G0 = div E - rho - rho_ion and max|rho_e| (interior);
-// mode 1: max |G - G0| over interior nodes into amax[1]
+// mode 0: store G0 = div E - rhoG - rho_ion and max|rho_e| (interior);
+// mode 1: max |G - G0| over interior nodes into amax[1].  rhoG is the
+// electron density, filtered like the current when the filter is on.
 template <typename R>
-__global__ __launch_bounds__(256) void k_gauss(const RunDev* __restrict__ rdp, int mode) {
+__global__ __launch_bounds__(256) void k_gauss(const RunDev* __restrict__ rdp, int mode, const double* rhoG) {
   __shared__ double sh[4];
   RunC& rd = *(RunC*)rdp;
   R* const* E = reinterpret_cast<R* const*>(rd.E[rd.ctr->fbuf]);
@@ -305,7 +349,7 @@ __global__ __launch_bounds__(256) void k_gauss(const RunDev* __restrict__ rdp, i
     const long long t = q / rd.nzf;
     const int i = (int)(t % rd.nx), j = (int)(t / rd.nx);
     if (rd.open && k > rd.nz) continue;
-    const double G = div_e(rd, E, k, i, j) - rd.rho_a[q] - rd.rho_ion;
+    const double G = div_e(rd, E, k, i, j) - rhoG[q] - rd.rho_ion;
     if (mode == 0) {
       rd.gauss0[q] = G;
       if (interior(rd, 0, k)) m = fmax(m, fabs(rd.rho_a[q]));
@@ -431,10 +475,23 @@ void launch_cont_post(int dims, int prec, const RunDev* rd, long long npts, long
   hipLaunchKernelGGL(k_cont_fin, dim3(1), dim3(1), 0, s, rd);
 }
 
-void launch_gauss(int prec, const RunDev* rd, long long npts, int mode, hipStream_t s) {
+void launch_gauss(int prec, const RunDev* rd, long long npts, int mode, const double* rhoG, hipStream_t s) {
   const unsigned g = gridfor(npts, 256, 4096);
-  if (prec) hipLaunchKernelGGL(k_gauss<double>, dim3(g), dim3(256), 0, s, rd, mode);
-  else hipLaunchKernelGGL(k_gauss<float>, dim3(g), dim3(256), 0, s, rd, mode);
+  if (prec) hipLaunchKernelGGL(k_gauss<double>, dim3(g), dim3(256), 0, s, rd, mode, rhoG);
+  else hipLaunchKernelGGL(k_gauss<float>, dim3(g), dim3(256), 0, s, rd, mode, rhoG);
+}
+
+const double* launch_filter_nodes(int dims, const RunDev* rd, long long npts, int stages, const double* rho,
+                                  double* t0, double* t1, hipStream_t s) {
+  const unsigned g = gridfor(npts, 256, 4096);
+  const double* src = rho;
+  for (int st = 0; st < stages; ++st) {
+    double* dst = (st & 1) ? t1 : t0;
+    if (dims == 3) hipLaunchKernelGGL(k_filter_nodes<3>, dim3(g), dim3(256), 0, s, rd, src, dst, st);
+    else hipLaunchKernelGGL(k_filter_nodes<2>, dim3(g), dim3(256), 0, s, rd, src, dst, st);
+    src = dst;
+  }
+  return src;
 }
 
 void launch_diag(int dims, int prec, const RunDev* rd, long long npts, long long cap, unsigned what,

@@ -934,13 +934,76 @@ __global__ __launch_bounds__(256) void k_efull(const BatchTable* __restrict__ bt
       bz_y = Bh[2][P.qym];
       bx_y = P.c_h ? Bh[0][P.qym] : R(0);
     }
-    const R jx = R((double)J[0][q] * jinv), jy = R((double)J[1][q] * jinv), jz = R((double)J[2][q] * jinv);
+    R jx, jy, jz;
+    if (rd.filter_stages > 0) {  // filtered current, already in physical units
+      const Arr3<R> F = PIC_ARR3(R, rd.jf[(rd.filter_stages - 1) & 1]);
+      jx = F[0][q];
+      jy = F[1][q];
+      jz = F[2][q];
+    } else {
+      jx = R((double)J[0][q] * jinv);
+      jy = R((double)J[1][q] * jinv);
+      jz = R((double)J[2][q] * jinv);
+    }
     En[0][q] = E[0][q] + dt * ((bz - bz_y) * idy - (by - by_z) * idz - jx);
     En[1][q] = E[1][q] + dt * ((bx - bx_z) * idz - (bz - bz_x) * idx - jy);
     En[2][q] = P.c_h ? E[2][q] + dt * ((by - by_x) * idx - (bx - bx_y) * idy - jz - R(rd.jion_z)) : R(0);
     Jnext[0][q] = 0;
     Jnext[1][q] = 0;
     Jnext[2][q] = 0;
+  }
+}
+
+// One stage of the low-pass current filter (between the deposit and the E
+// update).  Stage s is a three-point pass along axis s mod (number of axes)
+// on every current component's own staggered grid, with weights
+// (1/4, 1/2, 1/4) for the first passes x axes stages and (-N/4, 1 + N/2,
+// -N/4) for the compensating ones after them.  Stage 0 reads the deposited
+// fixed-point current times its scale, stage s > 0 reads the output of stage
+// s-1, and stage s writes jf[s & 1].  Open z: neighbours outside a
+// component's range count as zero, and points outside it are written as 0.
+// Runs of a batch with fewer stages skip the later ones.
+template <int DIM, typename R>
+__global__ __launch_bounds__(256) void k_filter(const BatchTable* __restrict__ bt, int stage) {
+  constexpr int NAX = DIM == 3 ? 3 : 2;
+  const XcdSplit xs(bt->cellblk);
+  for (long long w = xs.beg; w < xs.end; w += xs.stride) {
+    const int r = __builtin_amdgcn_readfirstlane(locate(bt->pre_cellblk, bt->n, w));
+    RunC& rd = *bt->run[r];
+    if (stage >= rd.filter_stages) continue;
+    FieldPt<DIM> P;
+    if (!P.init(rd, w - bt->pre_cellblk[r])) continue;
+    const int axis = stage % NAX;
+    const bool cpass = stage >= rd.filter_passes * NAX;
+    const R N = R(rd.filter_passes);
+    const R ws = cpass ? R(-0.25) * N : R(0.25);
+    const R wm = cpass ? R(1) + R(0.5) * N : R(0.5);
+    const unsigned q = P.q;
+    const unsigned qm = axis == 0 ? P.qzm : (axis == 1 ? P.qxm : P.qym);
+    const unsigned qp = axis == 0 ? P.qzp : (axis == 1 ? P.qxp : P.qyp);
+    const Arr3<long long> J = PIC_ARR3(long long, rd.J[rd.ctr->fbuf]);
+    const Arr3<R> src = PIC_ARR3(R, rd.jf[(stage + 1) & 1]);
+    const Arr3<R> dst = PIC_ARR3(R, rd.jf[stage & 1]);
+    const double jinv = rd.jinv;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      // z stagger of J like E: Jx, Jy on nodes, Jz on half points
+      const bool half = c == 2;
+      const bool cok = half ? P.c_h : true;
+      const bool mok = axis != 0 || P.zm_ok;
+      const bool pok = axis != 0 || (half ? P.zp_h : P.zp_n);
+      R v0 = R(0), vm = R(0), vp = R(0);
+      if (stage == 0) {
+        if (cok) v0 = R((double)J[c][q] * jinv);
+        if (mok) vm = R((double)J[c][qm] * jinv);
+        if (pok) vp = R((double)J[c][qp] * jinv);
+      } else {
+        if (cok) v0 = src[c][q];
+        if (mok) vm = src[c][qm];
+        if (pok) vp = src[c][qp];
+      }
+      dst[c][q] = cok ? wm * v0 + ws * (vm + vp) : R(0);
+    }
   }
 }
 
@@ -1017,17 +1080,19 @@ void launch_particles(int dims, int prec, int pusher, const BatchTable* bt, int 
 }
 
 template <int DIM, typename R>
-static void lf(const BatchTable* bt, int grid, hipStream_t s) {
+static void lf(const BatchTable* bt, int grid, int filter_stages, hipStream_t s) {
+  for (int st = 0; st < filter_stages; ++st)
+    hipLaunchKernelGGL((k_filter<DIM, R>), dim3(grid), dim3(256), 0, s, bt, st);
   hipLaunchKernelGGL((k_bhalf<DIM, R>), dim3(grid), dim3(256), 0, s, bt);
   hipLaunchKernelGGL((k_efull<DIM, R>), dim3(grid), dim3(256), 0, s, bt);
   hipLaunchKernelGGL((k_mur<R>), dim3(grid), dim3(256), 0, s, bt);
 }
 
-void launch_fields(int dims, int prec, const BatchTable* bt, int grid, hipStream_t s) {
+void launch_fields(int dims, int prec, const BatchTable* bt, int grid, int filter_stages, hipStream_t s) {
   if (dims == 3) {
-    if (prec) lf<3, double>(bt, grid, s); else lf<3, float>(bt, grid, s);
+    if (prec) lf<3, double>(bt, grid, filter_stages, s); else lf<3, float>(bt, grid, filter_stages, s);
   } else {
-    if (prec) lf<2, double>(bt, grid, s); else lf<2, float>(bt, grid, s);
+    if (prec) lf<2, double>(bt, grid, filter_stages, s); else lf<2, float>(bt, grid, filter_stages, s);
   }
 }
 

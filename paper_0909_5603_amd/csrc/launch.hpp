@@ -14,7 +14,7 @@ int grid_generic(int ncu);
 // one step, split in launches (all read their run set from the batch table)
 void launch_sort_chain(int dims, int prec, const BatchTable* bt, int nruns, int grid, hipStream_t s);
 void launch_particles(int dims, int prec, int pusher, const BatchTable* bt, int grid, hipStream_t s);
-void launch_fields(int dims, int prec, const BatchTable* bt, int grid, hipStream_t s);
+void launch_fields(int dims, int prec, const BatchTable* bt, int grid, int filter_stages, hipStream_t s);
 void launch_advance(const BatchTable* bt, int nruns, hipStream_t s);
 
 // initialisation (one run)
@@ -25,7 +25,11 @@ void launch_cont_pre(int dims, int prec, const RunDev* rd, long long npts, long 
 void launch_rho(int dims, int prec, const RunDev* rd, double* rho, long long npts, long long cap,
                 int use_snap, hipStream_t s);
 void launch_cont_post(int dims, int prec, const RunDev* rd, long long npts, long long cap, hipStream_t s);
-void launch_gauss(int prec, const RunDev* rd, long long npts, int mode, hipStream_t s);
+void launch_gauss(int prec, const RunDev* rd, long long npts, int mode, const double* rhoG, hipStream_t s);
+// the current filter's stages applied to a node scalar rho (ping-pong t0/t1);
+// returns the array holding the result (rho itself when stages = 0)
+const double* launch_filter_nodes(int dims, const RunDev* rd, long long npts, int stages, const double* rho,
+                                  double* t0, double* t1, hipStream_t s);
 void launch_diag(int dims, int prec, const RunDev* rd, long long npts, long long cap, unsigned what,
                  hipStream_t s);
 // B[dst] = B[src] + coef curl E[fbuf]; src/dst < 0 select fbuf / fbuf^1

@@ -58,6 +58,8 @@ struct Layout {
   size_t cell[2], off[2][3], u[2][3], pid[2];
   size_t tile_start, tile_count, tile_cursor, bbox[2];
   size_t rho_a, rho_b, gauss0, jlast[3], cell_snap, slowq;
+  size_t jf[2][3];  // filtered current (R), ping-pong; only with the filter
+  size_t ftmp[2];   // node scalar ping-pong of the filtered Gauss diagnostic (double)
   size_t zero_end;  // [0, zero_end) is cleared at init
   size_t total;
 };
@@ -89,6 +91,9 @@ pic_status derive(const pic_lab_params* p, Derived& d) {
   if (p->pusher != PIC_VAY && p->pusher != PIC_BORIS) return fail(PIC_EINVAL, "bad pusher");
   if (p->precision != PIC_FP32_SPLIT && p->precision != PIC_FP64) return fail(PIC_EINVAL, "bad precision");
   if (p->sort_every < 1) return fail(PIC_EINVAL, "sort_every must be >= 1");
+  if (p->filter_passes < 0 || p->filter_passes > 16) return fail(PIC_EINVAL, "filter_passes must be in 0..16");
+  if (p->filter_compensate != 0 && p->filter_compensate != 1)
+    return fail(PIC_EINVAL, "filter_compensate must be 0 or 1");
 
   double inv2 = 1.0 / (p->dz * p->dz) + 1.0 / (p->dx * p->dx);
   if (p->dims == 3) inv2 += 1.0 / (p->dy * p->dy);
@@ -182,6 +187,10 @@ void layout(const pic_lab_params* p, const Derived& d, Layout& L) {
   L.rho_b = cont ? take(sizeof(double) * d.npts) : NOPT;
   for (int c = 0; c < 3; ++c) L.jlast[c] = cont ? take(sizeof(double) * d.npts) : NOPT;
   L.cell_snap = cont ? take(sizeof(int) * d.capacity) : NOPT;
+  const bool filt = p->filter_passes > 0;
+  for (int b = 0; b < 2; ++b)
+    for (int c = 0; c < 3; ++c) L.jf[b][c] = filt ? take(d.rsz * d.npts) : NOPT;
+  for (int b = 0; b < 2; ++b) L.ftmp[b] = filt ? take(sizeof(double) * d.npts) : NOPT;
   const size_t cap = (size_t)d.capacity;
   L.slowq = take(sizeof(int) * cap);
   for (int b = 0; b < 2; ++b) {
@@ -215,7 +224,7 @@ struct pic_run {
   hipGraphExec_t g1n;  // one single-run step without it
   hipGraphExec_t gB;   // one batched step (this run's batch table), with the sort chain
   hipGraphExec_t gBn;  // the same without it
-  unsigned gB_flags;
+  int gB_fstages, gBn_fstages;  // current-filter stages the batched graphs were captured with
   // host mirror of the device step counter and of the step of the last
   // sort: the sort chain is enqueued only on steps where it has work (the
   // device decides again from its own counters, so the two must agree)
@@ -263,7 +272,7 @@ void host_advance(pic_run* r) {
 }
 
 // enqueue one step for the runs of a batch table
-void enqueue_step(pic_run* r0, const BatchTable* tab, bool cont, bool sort) {
+void enqueue_step(pic_run* r0, const BatchTable* tab, bool cont, bool sort, int fstages) {
   const int dims = r0->p.dims, prec = r0->p.precision;
   hipStream_t s = r0->stream;
   if (sort) launch_sort_chain(dims, prec, tab, MAX_BATCH, r0->ggen, s);
@@ -276,20 +285,31 @@ void enqueue_step(pic_run* r0, const BatchTable* tab, bool cont, bool sort) {
     launch_rho(dims, prec, r0->drd, at<double>(r0, r0->L.rho_b), r0->d.npts, r0->d.capacity, 1, s);
     launch_cont_post(dims, prec, r0->drd, r0->d.npts, r0->d.capacity, s);
   }
-  launch_fields(dims, prec, tab, r0->ggen, s);
+  launch_fields(dims, prec, tab, r0->ggen, fstages, s);
   launch_advance(tab, MAX_BATCH, s);
 }
 
-pic_status capture(pic_run* r, const BatchTable* tab, bool cont, bool sort, hipGraphExec_t* out) {
+pic_status capture(pic_run* r, const BatchTable* tab, bool cont, bool sort, int fstages,
+                   hipGraphExec_t* out) {
   hipGraph_t g = nullptr;
   HIPCHK(hipStreamBeginCapture(r->stream, hipStreamCaptureModeThreadLocal));
-  enqueue_step(r, tab, cont, sort);
+  enqueue_step(r, tab, cont, sort, fstages);
   hipError_t e = hipStreamEndCapture(r->stream, &g);
   if (e != hipSuccess) return fail(PIC_EHIP, "graph capture: %s", hipGetErrorString(e));
   e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
   (void)hipGraphDestroy(g);
   if (e != hipSuccess) return fail(PIC_EHIP, "graph instantiate: %s", hipGetErrorString(e));
   return PIC_OK;
+}
+
+// the electron density the Gauss diagnostic compares div E with: rho_a as
+// computed, or, with the current filter, rho_a filtered the same way
+// (enqueued on the run's stream)
+const double* gauss_rho(pic_run* r) {
+  const double* rho = at<double>(r, r->L.rho_a);
+  if (r->hrd.filter_stages == 0) return rho;
+  return launch_filter_nodes(r->p.dims, r->drd, r->d.npts, r->hrd.filter_stages, rho,
+                             at<double>(r, r->L.ftmp[0]), at<double>(r, r->L.ftmp[1]), r->stream);
 }
 
 pic_status read_counters(pic_run* r, Counters& c) {
@@ -396,6 +416,7 @@ pic_status pic_init_boosted(const pic_lab_params* p, void* dev_buf, size_t bytes
   r->g1n = nullptr;
   r->gB = nullptr;
   r->gBn = nullptr;
+  r->gB_fstages = r->gBn_fstages = 0;
   // the initial sort below runs at step 0
   r->hstep = 0;
   r->hlast_sort = 0;
@@ -428,6 +449,10 @@ pic_status pic_init_boosted(const pic_lab_params* p, void* dev_buf, size_t bytes
   h.gz = r->p.nz / 4;
   h.pusher = r->p.pusher;
   h.diag_flags = (int)r->p.diag_flags;
+  h.filter_passes = r->p.filter_passes;
+  h.filter_comp = r->p.filter_compensate;
+  h.filter_stages = r->p.filter_passes > 0
+                        ? (r->p.filter_passes + r->p.filter_compensate) * (r->p.dims == 3 ? 3 : 2) : 0;
   h.pol_axis = r->p.pol_axis;
   h.capacity = d.capacity;
   h.nperp = d.nperp;
@@ -466,7 +491,11 @@ pic_status pic_init_boosted(const pic_lab_params* p, void* dev_buf, size_t bytes
     h.J[0][c] = at<void>(r, L.J[0][c]);
     h.J[1][c] = at<void>(r, L.J[1][c]);
     h.jlast[c] = at<double>(r, L.jlast[c]);
+    h.jf[0][c] = at<void>(r, L.jf[0][c]);
+    h.jf[1][c] = at<void>(r, L.jf[1][c]);
   }
+  h.ftmp[0] = at<double>(r, L.ftmp[0]);
+  h.ftmp[1] = at<double>(r, L.ftmp[1]);
   for (int b = 0; b < 2; ++b) {
     h.cell[b] = at<int>(r, L.cell[b]);
     h.pid[b] = at<unsigned>(r, L.pid[b]);
@@ -513,7 +542,7 @@ pic_status pic_init_boosted(const pic_lab_params* p, void* dev_buf, size_t bytes
   }
   launch_sort_chain(r->p.dims, r->p.precision, r->dtab1, MAX_BATCH, r->ggen, s);
   launch_rho(r->p.dims, r->p.precision, r->drd, at<double>(r, L.rho_a), d.npts, d.capacity, 0, s);
-  launch_gauss(r->p.precision, r->drd, d.npts, 0, s);
+  launch_gauss(r->p.precision, r->drd, d.npts, 0, gauss_rho(r), s);
   INITCHK(hipGetLastError());
   INITCHK(hipStreamSynchronize(s));
 #undef INITCHK
@@ -541,12 +570,12 @@ pic_status pic_step(pic_run* r, int nsteps) {
     if (graph) {
       hipGraphExec_t& g = sort ? r->g1 : r->g1n;
       if (!g) {
-        pic_status st = capture(r, r->dtab1, cont, sort, &g);
+        pic_status st = capture(r, r->dtab1, cont, sort, r->hrd.filter_stages, &g);
         if (st != PIC_OK) return st;
       }
       HIPCHK(hipGraphLaunch(g, r->stream));
     } else {
-      enqueue_step(r, r->dtab1, cont, sort);
+      enqueue_step(r, r->dtab1, cont, sort, r->hrd.filter_stages);
     }
     host_advance(r);
   }
@@ -578,7 +607,7 @@ pic_status pic_step_timed(pic_run* r, int nsteps, double ms[4]) {
       (void)hipEventRecord(e[1], s);
       launch_particles(dims, prec, r->p.pusher, r->dtab1, r->gpart, s);
       (void)hipEventRecord(e[2], s);
-      launch_fields(dims, prec, r->dtab1, r->ggen, s);
+      launch_fields(dims, prec, r->dtab1, r->ggen, r->hrd.filter_stages, s);
       launch_advance(r->dtab1, MAX_BATCH, s);
       (void)hipEventRecord(e[3], s);
     }
@@ -634,16 +663,27 @@ pic_status pic_step_batch(pic_run* const* runs, const int* nsteps, int n) {
                             r0->stream));
     }
     bool sort = false;
-    for (pic_run* q : act) sort = sort || host_sort_due(q);
+    int fst = 0;  // filter stages: the most any run of the batch needs
+    for (pic_run* q : act) {
+      sort = sort || host_sort_due(q);
+      fst = std::max(fst, q->hrd.filter_stages);
+    }
     if (r0->use_graph && r0->stream != nullptr) {
       hipGraphExec_t& g = sort ? r0->gB : r0->gBn;
+      int& gst = sort ? r0->gB_fstages : r0->gBn_fstages;
+      if (g && gst != fst) {
+        HIPCHK(hipStreamSynchronize(r0->stream));
+        (void)hipGraphExecDestroy(g);
+        g = nullptr;
+      }
       if (!g) {
-        pic_status st = capture(r0, r0->dtabB, false, sort, &g);
+        pic_status st = capture(r0, r0->dtabB, false, sort, fst, &g);
         if (st != PIC_OK) return st;
+        gst = fst;
       }
       HIPCHK(hipGraphLaunch(g, r0->stream));
     } else {
-      enqueue_step(r0, r0->dtabB, false, sort);
+      enqueue_step(r0, r0->dtabB, false, sort, fst);
     }
     for (pic_run* q : act) host_advance(q);
   }
@@ -660,7 +700,7 @@ pic_status pic_diag(pic_run* r, unsigned what, pic_diag_out* out) {
   if (what & PIC_DIAG_GAUSS) {
     launch_rho(r->p.dims, r->p.precision, r->drd, at<double>(r, r->L.rho_a), r->d.npts, r->d.capacity,
                0, s);
-    launch_gauss(r->p.precision, r->drd, r->d.npts, 1, s);
+    launch_gauss(r->p.precision, r->drd, r->d.npts, 1, gauss_rho(r), s);
   }
   HIPCHK(hipGetLastError());
   Counters c;

@@ -97,6 +97,9 @@ struct RunDev {
   int ntz, ntx, nty, ntiles;
   int gx, gy, gz;       // wrap guards for tile-relative coordinates
   int pusher, diag_flags, pol_axis;
+  // current filter: passes, compensation flag, and number of one-axis
+  // stages ((passes + compensation) x axes; 0 = none)
+  int filter_passes, filter_comp, filter_stages, pad_f;
   long long capacity, nperp, npts, max_new;
   double dt, dz, dx, dy;
   double beta_b, gamma_b, dminus, dplus, weight, jion_z, rho_ion, u_th;
@@ -123,6 +126,8 @@ struct RunDev {
   PIC_G double* jlast[3];
   PIC_G int* cell_snap;
   PIC_G int* slowq;       // slots of particles deferred to the HBM path this step
+  PIC_G void* jf[2][3];   // filtered current (R): stage s writes jf[s & 1]
+  PIC_G double* ftmp[2];  // node scalar ping-pong (filtered Gauss diagnostic)
   PIC_G Counters* ctr;
 };
 

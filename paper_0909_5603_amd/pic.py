@@ -43,7 +43,8 @@ class pic_lab_params(ctypes.Structure):
         ("a0", ctypes.c_double), ("lambda0_um", ctypes.c_double), ("waist", ctypes.c_double),
         ("tau_lab", ctypes.c_double), ("pol_axis", ctypes.c_int), ("bc_z", ctypes.c_int),
         ("pusher", ctypes.c_int), ("precision", ctypes.c_int), ("sort_every", ctypes.c_int),
-        ("diag_flags", ctypes.c_uint),
+        ("diag_flags", ctypes.c_uint), ("filter_passes", ctypes.c_int),
+        ("filter_compensate", ctypes.c_int),
     ]
 
 
@@ -133,6 +134,8 @@ def make_params(cfg: dict, precision: str = "fp32", continuity: bool = False) ->
     p.precision = PIC_FP64 if precision == "fp64" else PIC_FP32_SPLIT
     p.sort_every = int(cfg.get("sort_every", 20))
     p.diag_flags = PIC_DIAGF_CONTINUITY if continuity else 0
+    p.filter_passes = int(cfg.get("filter_passes", 0))
+    p.filter_compensate = int(cfg.get("filter_compensate", 0))
     return p
 
 

@@ -49,7 +49,8 @@ def test_state_bytes_scale_with_the_workload(pic):
 @pytest.mark.parametrize("over,status", [
     (dict(nx=20), -1), (dict(dims=4), -1), (dict(cfl=1.0), -4), (dict(cfl=0.0), -4),
     (dict(gamma_boost=0.5), -1), (dict(ppc=-1), -1), (dict(sort_every=0), -1),
-    (dict(nz=4000), -1), (dict(pol_axis=3), -1),
+    (dict(nz=4000), -1), (dict(pol_axis=3), -1), (dict(filter_passes=17), -1),
+    (dict(filter_passes=-1), -1), (dict(filter_passes=1, filter_compensate=2), -1),
 ])
 def test_invalid_parameters(pic, over, status):
     cfg = workloads.config("c1", **over)
@@ -79,3 +80,11 @@ def test_copy_bench_rejects_bad_sizes_before_any_launch(pic):
     assert L.pic_copy_bench(None, None, 24, None) == -1  # not a multiple of 16
     assert L.pic_copy_bench(None, None, 32, None) == -1  # NULL buffers
     assert L.pic_copy_bench(8, 40, 32, None) == -1  # misaligned addresses: rejected before a launch
+
+
+def test_filter_buffers_are_allocated_only_when_used(pic):
+    base = pic.pic_state_bytes(pic.make_params(workloads.config("c1")))
+    filt = pic.pic_state_bytes(pic.make_params(workloads.config("c1", filter_passes=2)))
+    npts = (workloads.config("c1")["nz"] + 1) * workloads.config("c1")["nx"]
+    # two R-typed current sets (3 components) and two double node arrays
+    assert filt - base >= 2 * 3 * 4 * npts + 2 * 8 * npts
