@@ -188,6 +188,29 @@ def kernel_roofline(run, pic, nsteps, workload=None):
                 "sort_ms_per_step": ms["sort"], "step_ms_events": ms["step"]}
 
 
+def filter_cost(cfg, pic, torch, fields_ms_plain, nsteps=10, passes=1, compensate=1):
+    """The same workload with the low-pass current filter (binomial passes plus
+    compensation between deposit and field update): step and field-stage
+    times, and the filter's own share of the field stage."""
+    fcfg = dict(cfg, filter_passes=passes, filter_compensate=compensate)
+    run = pic.Run(fcfg, "fp32")
+    run.step(5)
+    run.synchronize()
+    ms = pic.pic_step_timed(run.handle, nsteps)
+    stages = (passes + compensate) * (3 if cfg["dims"] == 3 else 2)
+    npts = run.npts
+    run.close()
+    del run
+    torch.cuda.empty_cache()
+    fms = ms["fields"] - fields_ms_plain
+    # algorithmic bytes: stage 0 reads the fixed-point current (3 x 8 B) and
+    # writes the filtered one (3 x 4 B); later stages read and write 3 x 4 B
+    fbytes = npts * (36 + 24 * (stages - 1))
+    return {"passes": passes, "compensate": compensate, "stages": stages,
+            "ms_per_step_events": ms["step"], "fields_ms_per_step": ms["fields"],
+            "filter_ms_per_step": fms, "filter_GBs": fbytes / (fms * 1e-3) / 1e9 if fms > 0 else None}
+
+
 def serving(pic, torch, n_requests, budget_gib, chunk):
     from paper_0909_5603_amd import serve, workloads
 
@@ -228,6 +251,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-filter", action="store_true",
+                    help="skip the run with the low-pass current filter")
     ap.add_argument("--timing-steps", type=int, default=20)
     ap.add_argument("--serve-requests", type=int, default=64)
     ap.add_argument("--profile", action="store_true",
@@ -291,6 +316,11 @@ def main():
         run64.close()
         del run64
         torch.cuda.empty_cache()
+    if not args.no_filter:
+        fc = filter_cost(cfg, pic, torch, ms["fields"])
+        line["filter"] = fc
+        log(f"[filter] {fc['stages']} stages: {fc['filter_ms_per_step']:.3f} ms/step "
+            f"(step {fc['ms_per_step_events']:.3f} ms)")
     if not args.no_serving:
         res = serving(pic, torch, args.serve_requests, budget_gib=96.0, chunk=25)
         line["serving"] = res
