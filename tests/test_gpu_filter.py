@@ -43,6 +43,7 @@ def _frel(run, st):
 CASES = {
     "c1_n1": lambda: workloads.config("c1", filter_passes=1),
     "c1_n2_comp": lambda: workloads.config("c1", filter_passes=2, filter_compensate=1),
+    "c1_n5_comp": lambda: workloads.config("c1", filter_passes=5, filter_compensate=1),
     "3d_periodic_n1_comp": lambda: workloads.config(
         "c5", nz=32, nx=16, ny=16, ppc=2, gamma_boost=13.0, waist=0.3, bc_z="periodic",
         filter_passes=1, filter_compensate=1),
