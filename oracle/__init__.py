@@ -40,6 +40,9 @@ class Params(ctypes.Structure):
         ("tau_lab", ctypes.c_double), ("pol_axis", ctypes.c_int), ("bc_z", ctypes.c_int),
         ("pusher", ctypes.c_int), ("inject_every", ctypes.c_int), ("round_f32", ctypes.c_int),
         ("filter_passes", ctypes.c_int), ("filter_compensate", ctypes.c_int),
+        ("n_stations", ctypes.c_int), ("station_z0", ctypes.c_double),
+        ("station_dz", ctypes.c_double), ("station_stride", ctypes.c_int),
+        ("station_cap", ctypes.c_int),
     ]
 
 
@@ -96,6 +99,8 @@ def lib():
         L.ora_field_full_E.argtypes = [vp]
         L.ora_laser_lab.argtypes = [vp] + [ctypes.c_double] * 4 + [_D, _D]
         L.ora_filter_current.argtypes = [vp]
+        L.ora_station.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int64),
+                                  ctypes.POINTER(_D), ctypes.POINTER(_D)]
         L.ora_filter_nodes.argtypes = [vp, _D]
         L.ora_push_many.argtypes = [ctypes.c_int64, _D, _D, _D, _D, ctypes.c_double, ctypes.c_int, ctypes.c_int]
         _lib = L
@@ -167,6 +172,9 @@ def make_params(cfg: dict, round_f32: bool = False) -> Params:
     p.inject_every = int(cfg.get("sort_every", 20)); p.round_f32 = 1 if round_f32 else 0
     p.filter_passes = int(cfg.get("filter_passes", 0))
     p.filter_compensate = int(cfg.get("filter_compensate", 0))
+    p.n_stations = int(cfg.get("n_stations", 0))
+    p.station_z0 = float(cfg.get("station_z0", 0.0)); p.station_dz = float(cfg.get("station_dz", 0.0))
+    p.station_stride = int(cfg.get("station_stride", 1)); p.station_cap = int(cfg.get("station_cap", 0))
     return p
 
 
@@ -261,6 +269,20 @@ class State:
 
     def full_E(self):
         lib().ora_field_full_E(self._h)
+
+    def station(self, q: int):
+        """(lab times, data[sample, comp, ny/stride, nx/stride], samples taken)"""
+        n = ctypes.c_int64()
+        t, d = _D(), _D()
+        lib().ora_station(self._h, int(q), ctypes.byref(n), ctypes.byref(t), ctypes.byref(d))
+        p = self.params
+        st = max(p.station_stride, 1)
+        nys, nxs = (p.ny // st if p.dims == 3 else 1), p.nx // st
+        m = min(int(n.value), p.station_cap)
+        times = np.ctypeslib.as_array(t, shape=(max(p.station_cap, 1),))[:m].copy()
+        data = np.ctypeslib.as_array(d, shape=(max(p.station_cap, 1) * 6 * nys * nxs,))
+        data = data[:m * 6 * nys * nxs].reshape(m, 6, nys, nxs).copy()
+        return times, data, int(n.value)
 
     def filter_current(self):
         lib().ora_filter_current(self._h)

@@ -30,6 +30,10 @@ struct ora_state {
   uint32_t* id;
   int64_t next_col;
   int64_t step;
+  /* laboratory-frame stations */
+  double* st_data;    /* [station][sample][comp][ny/stride][nx/stride] */
+  double* st_time;    /* [station][sample] */
+  int64_t* st_count;  /* [station] */
 };
 
 /* Yee staggering per component: half-cell shift flags in (z, x, y).
@@ -674,6 +678,63 @@ void ora_filter_current(ora_state* s) {
 void ora_filter_nodes(const ora_state* s, double* a) { filter_array(s, a, zvalid_count(s, ORA_EX)); }
 
 /* ------------------------------------------------------------------------ */
+/* Laboratory-frame stations (Sec. 2: quantities are recorded at stations   */
+/* immobile in the laboratory, at a succession of times, with interpolation */
+/* because lab space-time points do not coincide with the boosted grid).    */
+/* A station is the plane z_lab = Z.  At boosted time t' it sits at         */
+/* z' = Z / gamma_b - beta_b t' (from z_lab = gamma_b (z' + beta_b t')),    */
+/* and the event it samples has lab time t_lab = gamma_b (t' + beta_b z')   */
+/* = t' / gamma_b + beta_b Z.  Every step, each station inside [0, L_z)     */
+/* records E^n, B^n at its plane: each component linearly interpolated in z */
+/* from its own staggered points (zero outside its range), transformed back */
+/* to the laboratory frame with the boost of velocity -beta_b.              */
+static double zinterp(const ora_state* s, int comp, double z, int i, int j) {
+  double u = z / s->p.dz - 0.5 * STAG[comp][0];
+  int k = (int)floor(u);
+  double f = u - k;
+  return (1.0 - f) * fval(s, comp, k, i, j) + f * fval(s, comp, k + 1, i, j);
+}
+
+static void record_stations(ora_state* s) {
+  const int S = s->p.n_stations, st = s->p.station_stride, T = s->p.station_cap;
+  if (S <= 0) return;
+  const int nxs = s->p.nx / st, nys = s->p.dims == 3 ? s->p.ny / st : 1;
+  const double Lz = s->p.nz * s->p.dz, tp = s->step * s->d.dt;
+  for (int q = 0; q < S; ++q) {
+    const double Z = s->p.station_z0 + q * s->p.station_dz;
+    const double zp = Z / s->d.gamma_b - s->d.beta_b * tp;
+    if (!(zp >= 0.0 && zp < Lz)) continue;
+    const int64_t t = s->st_count[q]++;
+    if (t >= T) continue;
+    s->st_time[(int64_t)q * T + t] = tp / s->d.gamma_b + s->d.beta_b * Z;
+    double* out = s->st_data + ((int64_t)q * T + t) * 6 * nys * nxs;
+    for (int js = 0; js < nys; ++js)
+      for (int is = 0; is < nxs; ++is) {
+        double Eb[3], Bb[3], El[3], Bl[3];
+        for (int c = 0; c < 3; ++c) {
+          Eb[c] = zinterp(s, ORA_EX + c, zp, is * st, js * st);
+          Bb[c] = zinterp(s, ORA_BX + c, zp, is * st, js * st);
+        }
+        ora_boost_fields(-s->d.beta_b, Eb, Bb, El, Bl);
+        for (int c = 0; c < 3; ++c) {
+          out[((int64_t)c * nys + js) * nxs + is] = El[c];
+          out[((int64_t)(3 + c) * nys + js) * nxs + is] = Bl[c];
+        }
+      }
+  }
+}
+
+void ora_station(const ora_state* s, int station, int64_t* count, const double** times,
+                 const double** data) {
+  const int T = s->p.station_cap;
+  const int nxs = s->p.nx / s->p.station_stride;
+  const int nys = s->p.dims == 3 ? s->p.ny / s->p.station_stride : 1;
+  *count = s->st_count[station];
+  *times = s->st_time + (int64_t)station * T;
+  *data = s->st_data + (int64_t)station * T * 6 * nys * nxs;
+}
+
+/* ------------------------------------------------------------------------ */
 /* diagnostics                                                              */
 static int interior_k(const ora_state* s, int comp, int k) {
   if (s->p.bc_z == ORA_BC_PERIODIC) return 1;
@@ -802,6 +863,14 @@ ora_state* ora_create(const ora_params* p) {
   s->npts = (int64_t)d->nzf * s->p.nx * s->p.ny;
   for (int c = 0; c < 9; ++c) s->F[c] = (double*)calloc(s->npts, sizeof(double));
   s->G0 = (double*)calloc(s->npts, sizeof(double));
+  if (s->p.n_stations > 0) {
+    if (s->p.station_stride < 1) s->p.station_stride = 1;
+    const int64_t per = 6 * (int64_t)(s->p.nx / s->p.station_stride) *
+                        (s->p.dims == 3 ? s->p.ny / s->p.station_stride : 1);
+    s->st_data = (double*)calloc((size_t)s->p.n_stations * s->p.station_cap * per, sizeof(double));
+    s->st_time = (double*)calloc((size_t)s->p.n_stations * s->p.station_cap, sizeof(double));
+    s->st_count = (int64_t*)calloc((size_t)s->p.n_stations, sizeof(int64_t));
+  }
   init_fields(s);
   if (p->ppc > 0) inject(s, 0);
   ora_reset_gauss_reference(s);
@@ -814,6 +883,7 @@ void ora_destroy(ora_state* s) {
   free(s->G0);
   free(s->pz); free(s->px); free(s->py);
   free(s->ux); free(s->uy); free(s->uz); free(s->id);
+  free(s->st_data); free(s->st_time); free(s->st_count);
   free(s);
 }
 
@@ -862,6 +932,7 @@ void ora_step(ora_state* s, int nsteps, double* cont_max) {
   const double ztop = (s->p.nz + s->d.reservoir + 2) * s->p.dz;
   for (int it = 0; it < nsteps; ++it) {
     if (open && s->step % s->p.inject_every == 0) inject(s, s->step);
+    record_stations(s);
     double *rho0 = NULL, *rho1 = NULL;
     if (cont_max) {
       rho0 = (double*)malloc(sizeof(double) * s->npts);

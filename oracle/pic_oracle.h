@@ -59,6 +59,12 @@ typedef struct {
   int round_f32;         /* round created offsets and momenta to FP32 */
   int filter_passes;     /* passes of the 1-2-1 current filter per axis (0: none) */
   int filter_compensate; /* 1: one compensating pass per axis after them */
+  /* laboratory-frame stations: planes z_lab = station_z0 + s station_dz,
+   * s < n_stations, sampled every step while inside the box, transverse
+   * stride station_stride, at most station_cap samples each */
+  int n_stations;
+  double station_z0, station_dz;
+  int station_stride, station_cap;
 } ora_params;
 
 typedef struct {
@@ -121,6 +127,13 @@ void ora_deposit(ora_state* s, const double p0[3], const double p1[3], double vy
 void ora_rho(const ora_state* s, double* rho);        /* electron charge, nodes */
 void ora_field_half_B(ora_state* s);                  /* B -= dt/2 curl E */
 void ora_field_full_E(ora_state* s);                  /* E += dt (curl B - J) */
+/* Station s's record: *count = samples taken (also those beyond the
+ * capacity, which are dropped); times[t] = laboratory time of sample t;
+ * data holds, per sample, the six laboratory-frame components
+ * Ex Ey Ez Bx By Bz, each on the [ny/stride][nx/stride] transverse points
+ * (i stride, j stride) of the component's own transverse stagger. */
+void ora_station(const ora_state* s, int station, int64_t* count, const double** times,
+                 const double** data);
 /* low-pass filter of the current as configured (filter_passes,
  * filter_compensate), applied by ora_step between the deposit and the field
  * update; exposed for its pins */
