@@ -93,6 +93,28 @@ typedef struct {
    * electron density.  0 = no filter. */
   int filter_passes;
   int filter_compensate;
+  /* Laboratory-frame stations (Sec. 2: a boosted-frame run is diagnosed at
+   * stations fixed in the laboratory, sampled at a succession of lab times,
+   * with interpolation because lab events do not fall on the boosted grid).
+   * Station q (0 <= q < n_stations) is the plane z_lab = Z_q = station_z0 +
+   * q station_dz (c/omega_p, lab frame).  At boosted time t' = n dt it sits
+   * at z' = Z_q / gamma_b - beta_b t' and the event it samples has lab time
+   * t_lab = t' / gamma_b + beta_b Z_q.  Every step whose z' lies in
+   * [0, nz dz), the station records E^n and B^n (integer time) at that z':
+   * each component linearly interpolated in z between its own staggered
+   * points (zero outside its range on an open axis, wrapped on a periodic
+   * one), on the transverse node indices (i, j) = (a, b) station_stride for
+   * a < nxs = nx / station_stride, b < nys = ny / station_stride (3D; nys = 1
+   * in 2D), then transformed back to the laboratory frame (boost of
+   * velocity -beta_b along z).  The first station_cap samples are stored in
+   * the run's buffer; later ones are counted but dropped.  n_stations = 0:
+   * none (the other station fields are then ignored).  Limits: n_stations
+   * <= 65536, 1 <= station_stride <= nx (and <= ny in 3D), station_cap >= 1,
+   * finite station_z0 and station_dz. */
+  int n_stations;
+  double station_z0, station_dz;
+  int station_stride;
+  int station_cap;
 } pic_lab_params;
 
 typedef struct pic_run pic_run; /* opaque host handle */
@@ -176,6 +198,19 @@ enum { PIC_F_EX = 0, PIC_F_EY, PIC_F_EZ, PIC_F_BX, PIC_F_BY, PIC_F_BZ,
  * current of the most recent step (only with PIC_DIAGF_CONTINUITY).
  * host must hold `npts` doubles.  Synchronises. */
 pic_status pic_read_fields(pic_run* run, int comp, double* host, int64_t npts);
+
+/* Copy the record of laboratory-frame station `station` (see
+ * pic_lab_params.n_stations) to host memory, in double precision:
+ *   *count = samples taken so far (stored or not);
+ *   times[m] = lab time of sample m;
+ *   data[((m * 6 + c) * nys + b) * nxs + a] = lab-frame component c
+ *     (Ex, Ey, Ez, Bx, By, Bz) at transverse node (a, b) station_stride,
+ * for m < min(*count, station_cap, max_samples).  times must hold
+ * max_samples doubles and data 6 nys nxs max_samples; either may be NULL
+ * when max_samples = 0.  Synchronises the run's stream.  PIC_EINVAL for a
+ * station index out of range or a run without stations. */
+pic_status pic_read_station(pic_run* run, int station, int64_t* count, double* times,
+                            double* data, int64_t max_samples);
 
 /* Boosted-frame quantities derived from the parameters. */
 typedef struct {

@@ -69,33 +69,6 @@ __global__ void k_laser(const RunDev* __restrict__ rdp) {
   }
 }
 
-// E value at integer index with the open/periodic z rules
-template <typename R>
-__device__ __forceinline__ double ev(RunC& rd, R* const* E, int c, int k, int i, int j) {
-  i = wrapi(i, rd.nx);
-  j = rd.dims == 3 ? wrapi(j, rd.ny) : 0;
-  if (rd.open) {
-    if (k < 0 || k >= zcount(rd, c)) return 0.0;
-  } else {
-    k = wrapi(k, rd.nz);
-  }
-  return (double)E[c][gidx(rd, k, i, j)];
-}
-
-// curl of E at the B point of component c (0,1,2 = x,y,z)
-template <typename R>
-__device__ __forceinline__ double curl_e(RunC& rd, R* const* E, int c, int k, int i, int j) {
-  const double idz = 1.0 / rd.dz, idx = 1.0 / rd.dx, idy = rd.dims == 3 ? 1.0 / rd.dy : 0.0;
-  if (c == 0)
-    return (ev(rd, E, 2, k, i, j + 1) - ev(rd, E, 2, k, i, j)) * idy -
-           (ev(rd, E, 1, k + 1, i, j) - ev(rd, E, 1, k, i, j)) * idz;
-  if (c == 1)
-    return (ev(rd, E, 0, k + 1, i, j) - ev(rd, E, 0, k, i, j)) * idz -
-           (ev(rd, E, 2, k, i + 1, j) - ev(rd, E, 2, k, i, j)) * idx;
-  return (ev(rd, E, 1, k, i + 1, j) - ev(rd, E, 1, k, i, j)) * idx -
-         (ev(rd, E, 0, k, i, j + 1) - ev(rd, E, 0, k, i, j)) * idy;
-}
-
 // B^{n+s dt} from B at the stored time: out = B + coef * curl E (valid points)
 template <typename R>
 __global__ void k_bshift(const RunDev* __restrict__ rdp, int src, int dst, double coef) {

@@ -16,6 +16,9 @@ void launch_sort_chain(int dims, int prec, const BatchTable* bt, int nruns, int 
 void launch_particles(int dims, int prec, int pusher, const BatchTable* bt, int grid, hipStream_t s);
 void launch_fields(int dims, int prec, const BatchTable* bt, int grid, int filter_stages, hipStream_t s);
 void launch_advance(const BatchTable* bt, int nruns, hipStream_t s);
+// laboratory-frame stations of every run of the table (before the advance);
+// max_items: station points of the largest station set in the table
+void launch_stations(int prec, const BatchTable* bt, long long max_items, int grid, hipStream_t s);
 
 // initialisation (one run)
 void launch_init_fields(int dims, int prec, const RunDev* rd, long long npts, hipStream_t s);

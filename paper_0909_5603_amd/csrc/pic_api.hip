@@ -50,6 +50,10 @@ struct Derived {
   int ntz, ntx, nty, ntiles;
   long long nperp, npts, capacity, max_new;
   size_t rsz;
+  // laboratory-frame stations: transverse samples per record (nxs, nys) and
+  // the points one station pass visits (n_stations nxs nys; 0 = none)
+  int st_nxs, st_nys;
+  long long st_items;
 };
 
 struct Layout {
@@ -60,6 +64,7 @@ struct Layout {
   size_t rho_a, rho_b, gauss0, jlast[3], cell_snap, slowq;
   size_t jf[2][3];  // filtered current (R), ping-pong; only with the filter
   size_t ftmp[2];   // node scalar ping-pong of the filtered Gauss diagnostic (double)
+  size_t st_count, st_time, st_data;  // stations (st_count is in the cleared range)
   size_t zero_end;  // [0, zero_end) is cleared at init
   size_t total;
 };
@@ -94,6 +99,14 @@ pic_status derive(const pic_lab_params* p, Derived& d) {
   if (p->filter_passes < 0 || p->filter_passes > 16) return fail(PIC_EINVAL, "filter_passes must be in 0..16");
   if (p->filter_compensate != 0 && p->filter_compensate != 1)
     return fail(PIC_EINVAL, "filter_compensate must be 0 or 1");
+  if (p->n_stations < 0 || p->n_stations > 65536) return fail(PIC_EINVAL, "n_stations must be in 0..65536");
+  if (p->n_stations > 0) {
+    if (p->station_stride < 1 || p->station_stride > p->nx || (p->dims == 3 && p->station_stride > ny))
+      return fail(PIC_EINVAL, "station_stride must be in [1, nx] (and <= ny in 3D)");
+    if (p->station_cap < 1) return fail(PIC_EINVAL, "station_cap must be >= 1");
+    if (!std::isfinite(p->station_z0) || !std::isfinite(p->station_dz))
+      return fail(PIC_EINVAL, "station_z0 and station_dz must be finite");
+  }
 
   double inv2 = 1.0 / (p->dz * p->dz) + 1.0 / (p->dx * p->dx);
   if (p->dims == 3) inv2 += 1.0 / (p->dy * p->dy);
@@ -153,6 +166,16 @@ pic_status derive(const pic_lab_params* p, Derived& d) {
     }
   }
   d.rsz = p->precision == PIC_FP64 ? sizeof(double) : sizeof(float);
+  d.st_nxs = d.st_nys = 0;
+  d.st_items = 0;
+  if (p->n_stations > 0) {
+    d.st_nxs = p->nx / p->station_stride;
+    d.st_nys = p->dims == 3 ? ny / p->station_stride : 1;
+    d.st_items = (long long)p->n_stations * d.st_nxs * d.st_nys;
+    // 6 doubles per point and sample: keep the record addressable
+    const double rec = 48.0 * (double)d.st_items * (double)p->station_cap;
+    if (rec > 64.0 * (1LL << 30)) return fail(PIC_EINVAL, "station record of %.3g bytes exceeds 64 GiB", rec);
+  }
   return PIC_OK;
 }
 
@@ -180,7 +203,11 @@ void layout(const pic_lab_params* p, const Derived& d, Layout& L) {
   L.tile_cursor = take(sizeof(int) * d.ntiles);
   L.bbox[0] = take(sizeof(int) * 6 * d.ntiles);
   L.bbox[1] = take(sizeof(int) * 6 * d.ntiles);
+  const bool stn = p->n_stations > 0;
+  L.st_count = stn ? take(sizeof(long long) * p->n_stations) : NOPT;
   L.zero_end = (o + 255) & ~(size_t)255;
+  L.st_time = stn ? take(sizeof(double) * p->n_stations * (size_t)p->station_cap) : NOPT;
+  L.st_data = stn ? take(sizeof(double) * 6 * (size_t)d.st_items * (size_t)p->station_cap) : NOPT;
   L.rho_a = take(sizeof(double) * d.npts);
   L.gauss0 = take(sizeof(double) * d.npts);
   const bool cont = (p->diag_flags & PIC_DIAGF_CONTINUITY) != 0;
@@ -225,6 +252,7 @@ struct pic_run {
   hipGraphExec_t gB;   // one batched step (this run's batch table), with the sort chain
   hipGraphExec_t gBn;  // the same without it
   int gB_fstages, gBn_fstages;  // current-filter stages the batched graphs were captured with
+  long long gB_stitems, gBn_stitems;  // and station points
   // host mirror of the device step counter and of the step of the last
   // sort: the sort chain is enqueued only on steps where it has work (the
   // device decides again from its own counters, so the two must agree)
@@ -272,7 +300,9 @@ void host_advance(pic_run* r) {
 }
 
 // enqueue one step for the runs of a batch table
-void enqueue_step(pic_run* r0, const BatchTable* tab, bool cont, bool sort, int fstages) {
+// st_items: station points of the largest station set in the table (0: no
+// run of the table has stations)
+void enqueue_step(pic_run* r0, const BatchTable* tab, bool cont, bool sort, int fstages, long long st_items) {
   const int dims = r0->p.dims, prec = r0->p.precision;
   hipStream_t s = r0->stream;
   if (sort) launch_sort_chain(dims, prec, tab, MAX_BATCH, r0->ggen, s);
@@ -286,14 +316,16 @@ void enqueue_step(pic_run* r0, const BatchTable* tab, bool cont, bool sort, int 
     launch_cont_post(dims, prec, r0->drd, r0->d.npts, r0->d.capacity, s);
   }
   launch_fields(dims, prec, tab, r0->ggen, fstages, s);
+  // E[fbuf] = E^n and B[fbuf] = B^{n-1/2} are intact until the advance flips fbuf
+  if (st_items > 0) launch_stations(prec, tab, st_items, r0->ggen, s);
   launch_advance(tab, MAX_BATCH, s);
 }
 
 pic_status capture(pic_run* r, const BatchTable* tab, bool cont, bool sort, int fstages,
-                   hipGraphExec_t* out) {
+                   long long st_items, hipGraphExec_t* out) {
   hipGraph_t g = nullptr;
   HIPCHK(hipStreamBeginCapture(r->stream, hipStreamCaptureModeThreadLocal));
-  enqueue_step(r, tab, cont, sort, fstages);
+  enqueue_step(r, tab, cont, sort, fstages, st_items);
   hipError_t e = hipStreamEndCapture(r->stream, &g);
   if (e != hipSuccess) return fail(PIC_EHIP, "graph capture: %s", hipGetErrorString(e));
   e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
@@ -417,6 +449,7 @@ pic_status pic_init_boosted(const pic_lab_params* p, void* dev_buf, size_t bytes
   r->gB = nullptr;
   r->gBn = nullptr;
   r->gB_fstages = r->gBn_fstages = 0;
+  r->gB_stitems = r->gBn_stitems = 0;
   // the initial sort below runs at step 0
   r->hstep = 0;
   r->hlast_sort = 0;
@@ -496,6 +529,18 @@ pic_status pic_init_boosted(const pic_lab_params* p, void* dev_buf, size_t bytes
   }
   h.ftmp[0] = at<double>(r, L.ftmp[0]);
   h.ftmp[1] = at<double>(r, L.ftmp[1]);
+  h.n_stations = r->p.n_stations;
+  if (h.n_stations > 0) {
+    h.st_stride = r->p.station_stride;
+    h.st_cap = r->p.station_cap;
+    h.st_nxs = d.st_nxs;
+    h.st_nys = d.st_nys;
+    h.st_z0 = r->p.station_z0;
+    h.st_dz = r->p.station_dz;
+    h.st_count = at<long long>(r, L.st_count);
+    h.st_time = at<double>(r, L.st_time);
+    h.st_data = at<double>(r, L.st_data);
+  }
   for (int b = 0; b < 2; ++b) {
     h.cell[b] = at<int>(r, L.cell[b]);
     h.pid[b] = at<unsigned>(r, L.pid[b]);
@@ -570,12 +615,12 @@ pic_status pic_step(pic_run* r, int nsteps) {
     if (graph) {
       hipGraphExec_t& g = sort ? r->g1 : r->g1n;
       if (!g) {
-        pic_status st = capture(r, r->dtab1, cont, sort, r->hrd.filter_stages, &g);
+        pic_status st = capture(r, r->dtab1, cont, sort, r->hrd.filter_stages, r->d.st_items, &g);
         if (st != PIC_OK) return st;
       }
       HIPCHK(hipGraphLaunch(g, r->stream));
     } else {
-      enqueue_step(r, r->dtab1, cont, sort, r->hrd.filter_stages);
+      enqueue_step(r, r->dtab1, cont, sort, r->hrd.filter_stages, r->d.st_items);
     }
     host_advance(r);
   }
@@ -608,6 +653,7 @@ pic_status pic_step_timed(pic_run* r, int nsteps, double ms[4]) {
       launch_particles(dims, prec, r->p.pusher, r->dtab1, r->gpart, s);
       (void)hipEventRecord(e[2], s);
       launch_fields(dims, prec, r->dtab1, r->ggen, r->hrd.filter_stages, s);
+      if (r->d.st_items > 0) launch_stations(prec, r->dtab1, r->d.st_items, r->ggen, s);
       launch_advance(r->dtab1, MAX_BATCH, s);
       (void)hipEventRecord(e[3], s);
     }
@@ -663,27 +709,31 @@ pic_status pic_step_batch(pic_run* const* runs, const int* nsteps, int n) {
                             r0->stream));
     }
     bool sort = false;
-    int fst = 0;  // filter stages: the most any run of the batch needs
+    int fst = 0;           // filter stages: the most any run of the batch needs
+    long long sti = 0;     // station points: the most any run of the batch has
     for (pic_run* q : act) {
       sort = sort || host_sort_due(q);
       fst = std::max(fst, q->hrd.filter_stages);
+      sti = std::max(sti, q->d.st_items);
     }
     if (r0->use_graph && r0->stream != nullptr) {
       hipGraphExec_t& g = sort ? r0->gB : r0->gBn;
       int& gst = sort ? r0->gB_fstages : r0->gBn_fstages;
-      if (g && gst != fst) {
+      long long& gsi = sort ? r0->gB_stitems : r0->gBn_stitems;
+      if (g && (gst != fst || gsi != sti)) {
         HIPCHK(hipStreamSynchronize(r0->stream));
         (void)hipGraphExecDestroy(g);
         g = nullptr;
       }
       if (!g) {
-        pic_status st = capture(r0, r0->dtabB, false, sort, fst, &g);
+        pic_status st = capture(r0, r0->dtabB, false, sort, fst, sti, &g);
         if (st != PIC_OK) return st;
         gst = fst;
+        gsi = sti;
       }
       HIPCHK(hipGraphLaunch(g, r0->stream));
     } else {
-      enqueue_step(r0, r0->dtabB, false, sort, fst);
+      enqueue_step(r0, r0->dtabB, false, sort, fst, sti);
     }
     for (pic_run* q : act) host_advance(q);
   }
@@ -805,6 +855,32 @@ pic_status pic_read_fields(pic_run* r, int comp, double* host, int64_t npts) {
     std::vector<float> tmp(n);
     HIPCHK(hipMemcpy(tmp.data(), src, sizeof(float) * n, hipMemcpyDeviceToHost));
     for (size_t q = 0; q < n; ++q) host[q] = tmp[q];
+  }
+  return PIC_OK;
+}
+
+pic_status pic_read_station(pic_run* r, int station, int64_t* count, double* times, double* data,
+                            int64_t max_samples) {
+  if (!r || !count) return fail(PIC_EINVAL, "NULL argument");
+  if (r->p.n_stations <= 0) return fail(PIC_EINVAL, "the run has no stations");
+  if (station < 0 || station >= r->p.n_stations)
+    return fail(PIC_EINVAL, "station %d outside [0, %d)", station, r->p.n_stations);
+  if (max_samples < 0) return fail(PIC_EINVAL, "max_samples < 0");
+  if (max_samples > 0 && (!times || !data)) return fail(PIC_EINVAL, "times or data is NULL");
+  Counters c;
+  pic_status st = read_counters(r, c);
+  if (st != PIC_OK) return st;
+  long long n = 0;
+  HIPCHK(hipMemcpy(&n, r->hrd.st_count + station, sizeof(n), hipMemcpyDeviceToHost));
+  *count = n;
+  const long long cap = r->p.station_cap;
+  const long long m = std::min(std::min(n, cap), (long long)max_samples);
+  if (m > 0) {
+    const size_t rec = 6 * (size_t)r->d.st_nxs * (size_t)r->d.st_nys;
+    HIPCHK(hipMemcpy(times, r->hrd.st_time + (size_t)station * cap, sizeof(double) * m,
+                     hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(data, r->hrd.st_data + (size_t)station * cap * rec, sizeof(double) * m * rec,
+                     hipMemcpyDeviceToHost));
   }
   return PIC_OK;
 }

@@ -129,6 +129,13 @@ struct RunDev {
   PIC_G void* jf[2][3];   // filtered current (R): stage s writes jf[s & 1]
   PIC_G double* ftmp[2];  // node scalar ping-pong (filtered Gauss diagnostic)
   PIC_G Counters* ctr;
+  // laboratory-frame stations: count, first z (lab), spacing, transverse
+  // stride, stored samples per station and transverse samples per record
+  int n_stations, st_stride, st_cap, st_nxs, st_nys, pad_s;
+  double st_z0, st_dz;
+  PIC_G double* st_time;      // [station][st_cap] lab times
+  PIC_G double* st_data;      // [station][st_cap][6][st_nys][st_nxs] lab fields
+  PIC_G long long* st_count;  // [station] samples taken
 };
 
 // a run descriptor as the kernels see it (read-only, constant address space)
@@ -219,6 +226,33 @@ __device__ __forceinline__ int zcount(RunC& r, int comp) {
 
 __device__ __forceinline__ long long gidx(RunC& r, int k, int i, int j) {
   return ((long long)j * r.nx + i) * r.nzf + k;
+}
+
+// E value at integer index with the open/periodic z rules
+template <typename R>
+__device__ __forceinline__ double ev(RunC& rd, R* const* E, int c, int k, int i, int j) {
+  i = wrapi(i, rd.nx);
+  j = rd.dims == 3 ? wrapi(j, rd.ny) : 0;
+  if (rd.open) {
+    if (k < 0 || k >= zcount(rd, c)) return 0.0;
+  } else {
+    k = wrapi(k, rd.nz);
+  }
+  return (double)E[c][gidx(rd, k, i, j)];
+}
+
+// curl of E at the B point of component c (0,1,2 = x,y,z)
+template <typename R>
+__device__ __forceinline__ double curl_e(RunC& rd, R* const* E, int c, int k, int i, int j) {
+  const double idz = 1.0 / rd.dz, idx = 1.0 / rd.dx, idy = rd.dims == 3 ? 1.0 / rd.dy : 0.0;
+  if (c == 0)
+    return (ev(rd, E, 2, k, i, j + 1) - ev(rd, E, 2, k, i, j)) * idy -
+           (ev(rd, E, 1, k + 1, i, j) - ev(rd, E, 1, k, i, j)) * idz;
+  if (c == 1)
+    return (ev(rd, E, 0, k + 1, i, j) - ev(rd, E, 0, k, i, j)) * idz -
+           (ev(rd, E, 2, k, i + 1, j) - ev(rd, E, 2, k, i, j)) * idx;
+  return (ev(rd, E, 1, k, i + 1, j) - ev(rd, E, 1, k, i, j)) * idx -
+         (ev(rd, E, 0, k, i, j + 1) - ev(rd, E, 0, k, i, j)) * idy;
 }
 
 // Philox4x64-10 (Salmon et al., SC'11)

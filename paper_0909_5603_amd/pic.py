@@ -44,7 +44,9 @@ class pic_lab_params(ctypes.Structure):
         ("tau_lab", ctypes.c_double), ("pol_axis", ctypes.c_int), ("bc_z", ctypes.c_int),
         ("pusher", ctypes.c_int), ("precision", ctypes.c_int), ("sort_every", ctypes.c_int),
         ("diag_flags", ctypes.c_uint), ("filter_passes", ctypes.c_int),
-        ("filter_compensate", ctypes.c_int),
+        ("filter_compensate", ctypes.c_int), ("n_stations", ctypes.c_int),
+        ("station_z0", ctypes.c_double), ("station_dz", ctypes.c_double),
+        ("station_stride", ctypes.c_int), ("station_cap", ctypes.c_int),
     ]
 
 
@@ -66,7 +68,7 @@ class pic_derived(ctypes.Structure):
 
 # names declared in include/pic.h, in order
 EXPORTS = ["pic_state_bytes", "pic_init_boosted", "pic_step", "pic_step_timed", "pic_step_batch", "pic_diag",
-           "pic_particle_count", "pic_read_particles", "pic_read_fields", "pic_get_derived",
+           "pic_particle_count", "pic_read_particles", "pic_read_fields", "pic_read_station", "pic_get_derived",
            "pic_set_option", "pic_free", "pic_last_error", "pic_push_bench", "pic_copy_bench"]
 
 _lib = None
@@ -92,6 +94,7 @@ def lib():
     L.pic_read_particles.argtypes = [vp, i64, i64] + [dp] * 6 + [ctypes.POINTER(ctypes.c_uint32),
                                                               ctypes.POINTER(i64)]
     L.pic_read_fields.argtypes = [vp, ctypes.c_int, dp, i64]
+    L.pic_read_station.argtypes = [vp, ctypes.c_int, ctypes.POINTER(i64), dp, dp, i64]
     L.pic_get_derived.argtypes = [vp, ctypes.POINTER(pic_derived)]
     L.pic_set_option.argtypes = [vp, ctypes.c_int, ctypes.c_int]
     L.pic_free.argtypes = [vp]
@@ -136,6 +139,9 @@ def make_params(cfg: dict, precision: str = "fp32", continuity: bool = False) ->
     p.diag_flags = PIC_DIAGF_CONTINUITY if continuity else 0
     p.filter_passes = int(cfg.get("filter_passes", 0))
     p.filter_compensate = int(cfg.get("filter_compensate", 0))
+    p.n_stations = int(cfg.get("n_stations", 0))
+    p.station_z0 = float(cfg.get("station_z0", 0.0)); p.station_dz = float(cfg.get("station_dz", 0.0))
+    p.station_stride = int(cfg.get("station_stride", 1)); p.station_cap = int(cfg.get("station_cap", 0))
     return p
 
 
@@ -207,6 +213,26 @@ def pic_read_fields(run: int, comp: int, npts: int) -> np.ndarray:
     return out
 
 
+def station_shape(params: pic_lab_params):
+    """(nys, nxs): transverse samples of one station record."""
+    st = max(int(params.station_stride), 1)
+    return (params.ny // st if params.dims == 3 else 1), params.nx // st
+
+
+def pic_read_station(run: int, params: pic_lab_params, station: int, max_samples: int | None = None):
+    """(lab times[m], data[m, 6, nys, nxs], samples taken) of one station."""
+    nys, nxs = station_shape(params)
+    m = int(params.station_cap if max_samples is None else max_samples)
+    times = np.zeros(max(m, 1))
+    data = np.zeros(max(m, 1) * 6 * nys * nxs)
+    n = ctypes.c_int64()
+    dpp = ctypes.POINTER(ctypes.c_double)
+    _check(lib().pic_read_station(ctypes.c_void_p(run), int(station), ctypes.byref(n),
+                                  times.ctypes.data_as(dpp), data.ctypes.data_as(dpp), m))
+    k = min(int(n.value), int(params.station_cap), m)
+    return times[:k].copy(), data[:k * 6 * nys * nxs].reshape(k, 6, nys, nxs).copy(), int(n.value)
+
+
 def pic_get_derived(run: int) -> dict:
     d = pic_derived()
     _check(lib().pic_get_derived(ctypes.c_void_p(run), ctypes.byref(d)))
@@ -271,6 +297,9 @@ class Run:
 
     def field(self, comp: int) -> np.ndarray:
         return pic_read_fields(self.handle, comp, self.npts).reshape(self.shape)
+
+    def station(self, q: int, max_samples: int | None = None):
+        return pic_read_station(self.handle, self.params, q, max_samples)
 
     def synchronize(self):
         self.stream.synchronize()

@@ -88,3 +88,41 @@ def test_filter_buffers_are_allocated_only_when_used(pic):
     npts = (workloads.config("c1")["nz"] + 1) * workloads.config("c1")["nx"]
     # two R-typed current sets (3 components) and two double node arrays
     assert filt - base >= 2 * 3 * 4 * npts + 2 * 8 * npts
+
+
+@pytest.mark.parametrize("over", [
+    dict(n_stations=-1), dict(n_stations=65537), dict(n_stations=2, station_stride=0, station_cap=4),
+    dict(n_stations=2, station_stride=10_000, station_cap=4), dict(n_stations=2, station_stride=1, station_cap=0),
+    dict(n_stations=2, station_stride=1, station_cap=4, station_z0=float("nan")),
+    dict(n_stations=2, station_stride=1, station_cap=4, station_dz=float("inf")),
+    dict(n_stations=65536, station_stride=1, station_cap=1 << 20),  # record beyond 64 GiB
+])
+def test_invalid_station_parameters(pic, over):
+    with pytest.raises(pic.PicError) as e:
+        pic.pic_state_bytes(pic.make_params(workloads.config("c1", **over)))
+    assert e.value.status == -1
+    assert "station" in pic.pic_last_error()
+
+
+def test_station_record_size(pic):
+    cfg = workloads.config("c5", nz=32, nx=16, ny=16, ppc=1)
+    base = pic.pic_state_bytes(pic.make_params(cfg))
+    S, stride, cap = 3, 4, 50
+    withst = pic.pic_state_bytes(pic.make_params(dict(cfg, n_stations=S, station_stride=stride,
+                                                      station_cap=cap)))
+    p = pic.make_params(dict(cfg, n_stations=S, station_stride=stride, station_cap=cap))
+    nys, nxs = pic.station_shape(p)
+    assert (nys, nxs) == (4, 4)
+    rec = S * cap * (6 * nys * nxs + 1) * 8 + S * 8
+    assert rec <= withst - base <= rec + 4 * 256
+    # 2D: one transverse row
+    p2 = pic.make_params(workloads.config("c1", n_stations=1, station_stride=2, station_cap=3))
+    assert pic.station_shape(p2) == (1, workloads.config("c1")["nx"] // 2)
+
+
+def test_read_station_argument_checks(pic):
+    import ctypes
+
+    L = pic.lib()
+    n = ctypes.c_int64()
+    assert L.pic_read_station(None, 0, ctypes.byref(n), None, None, 0) == -1
