@@ -42,7 +42,8 @@ class Params(ctypes.Structure):
         ("filter_passes", ctypes.c_int), ("filter_compensate", ctypes.c_int),
         ("n_stations", ctypes.c_int), ("station_z0", ctypes.c_double),
         ("station_dz", ctypes.c_double), ("station_stride", ctypes.c_int),
-        ("station_cap", ctypes.c_int),
+        ("station_cap", ctypes.c_int), ("laser_antenna", ctypes.c_int),
+        ("antenna_z_lab", ctypes.c_double), ("antenna_t_peak", ctypes.c_double),
     ]
 
 
@@ -175,6 +176,9 @@ def make_params(cfg: dict, round_f32: bool = False) -> Params:
     p.n_stations = int(cfg.get("n_stations", 0))
     p.station_z0 = float(cfg.get("station_z0", 0.0)); p.station_dz = float(cfg.get("station_dz", 0.0))
     p.station_stride = int(cfg.get("station_stride", 1)); p.station_cap = int(cfg.get("station_cap", 0))
+    p.laser_antenna = int(cfg.get("laser_antenna", 0))
+    p.antenna_z_lab = float(cfg.get("antenna_z_lab", 0.0))
+    p.antenna_t_peak = float(cfg.get("antenna_t_peak", 0.0))
     return p
 
 

@@ -379,7 +379,106 @@ void ora_rho(const ora_state* s, double* rho) {
 static int zlimit(const ora_state* s, int comp) { return zvalid_count(s, comp); }
 
 /* B -= dt/2 curl E  (one half step) */
-void ora_field_half_B(ora_state* s) {
+/* ------------------------------------------------------------------------ */
+/* Laser antenna (Sec. 2: the laser is injected at a plane fixed in the     */
+/* laboratory frame, which drifts in the boosted frame).  The lab plane     */
+/* z = Z_a sits at z'_a(t') = Z_a / gamma_b - beta_b t' and moves at        */
+/* -beta_b.  Wanted: the boosted incident wave (E_i, B_i) above the plane   */
+/* and nothing below, i.e. the field H (E_i, B_i) with H(z', t') = 1 where  */
+/* z' > z'_a(t'), else 0.  In the continuum the step's derivatives leave    */
+/* surface sources on the plane (an electric current J and a magnetic       */
+/* current M in dB/dt = -curl E - M).  On the grid they are taken as what   */
+/* the discrete update needs to carry H (E_i, B_i) from one time level to   */
+/* the next:                                                                */
+/*   J^{n+1/2} = curl_h (H B_i)^{n+1/2} - ((H E_i)^{n+1} - (H E_i)^n) / dt, */
+/*   M^n = -curl_h (H E_i)^n - ((H B_i)^{n+1/2} - (H B_i)^{n-1/2}) / dt,    */
+/* with curl_h the Yee differences of the field update, each point's H at   */
+/* its own staggered z and time, and the source kept only at points whose   */
+/* update involves both sides of the plane (elsewhere it is zero: above the */
+/* plane the field evolves by the Yee update alone).  This is exact for any */
+/* speed of the plane, where spreading a moving delta over the grid is not. */
+/* The incident wave is the lab pulse evaluated at the lab event of each    */
+/* grid point and boosted.  The antenna acts at level n while              */
+/* 2 dz <= z'_a(n dt) < (nz - 2) dz; at t' = 0 the box holds H (E_i, B_i).  */
+static double antenna_z(const ora_state* s, double t) {
+  return s->p.antenna_z_lab / s->d.gamma_b - s->d.beta_b * t;
+}
+
+/* H times the incident boosted field, component comp at its point (k, i, j)
+ * at boosted time t; *hmin / *hmax track the H values seen */
+static double hinc(const ora_state* s, int comp, int k, int i, int j, double t, int* hmin, int* hmax) {
+  const double z = (k + 0.5 * STAG[comp][0]) * s->p.dz;
+  const int h = z > antenna_z(s, t) ? 1 : 0;
+  if (h < *hmin) *hmin = h;
+  if (h > *hmax) *hmax = h;
+  if (!h) return 0.0;
+  i = wrapi(i, s->p.nx);
+  j = s->p.dims == 3 ? wrapi(j, s->p.ny) : 0;
+  const double x = (i + 0.5 * STAG[comp][1]) * s->p.dx;
+  const double y = s->p.dims == 3 ? (j + 0.5 * STAG[comp][2]) * s->p.dy : 0.0;
+  double El[3], Bl[3], Ei[3], Bi[3];
+  ora_laser_lab(s, s->d.gamma_b * (z + s->d.beta_b * t), s->d.gamma_b * (t + s->d.beta_b * z), x, y, El, Bl);
+  ora_boost_fields(s->d.beta_b, El, Bl, Ei, Bi);
+  return comp < 3 ? Ei[comp] : Bi[comp - 3];
+}
+
+static int antenna_on(const ora_state* s, int64_t n) {
+  if (!s->p.laser_antenna || s->p.a0 == 0.0) return 0;
+  const double za = antenna_z(s, n * s->d.dt);
+  return za >= 2.0 * s->p.dz && za < (s->p.nz - 2) * s->p.dz;
+}
+
+/* J^{n+1/2} (comp = ORA_EX..EZ) or M^n (comp = ORA_BX..BZ) at (k, i, j);
+ * *straddle (if given) tells whether the point's update involves both sides */
+static double antenna_source_s(const ora_state* s, int comp, int64_t n, int k, int i, int j, int* straddle) {
+  if (straddle) *straddle = 0;
+  if (!antenna_on(s, n)) return 0.0;
+  const double dt = s->d.dt;
+  const double z = (k + 0.5 * STAG[comp][0]) * s->p.dz;
+  if (fabs(z - antenna_z(s, n * dt)) > 3.0 * s->p.dz) return 0.0; /* cannot straddle */
+  const double idz = 1.0 / s->p.dz, idx = 1.0 / s->p.dx;
+  const double idy = s->p.dims == 3 ? 1.0 / s->p.dy : 0.0;
+  int lo = 1, hi = 0;
+  double r;
+  if (comp <= ORA_EZ) {
+    const double th = (n + 0.5) * dt, t0 = n * dt, t1 = (n + 1) * dt;
+    double curl;
+    if (comp == ORA_EX)
+      curl = (hinc(s, ORA_BZ, k, i, j, th, &lo, &hi) - hinc(s, ORA_BZ, k, i, j - 1, th, &lo, &hi)) * idy -
+             (hinc(s, ORA_BY, k, i, j, th, &lo, &hi) - hinc(s, ORA_BY, k - 1, i, j, th, &lo, &hi)) * idz;
+    else if (comp == ORA_EY)
+      curl = (hinc(s, ORA_BX, k, i, j, th, &lo, &hi) - hinc(s, ORA_BX, k - 1, i, j, th, &lo, &hi)) * idz -
+             (hinc(s, ORA_BZ, k, i, j, th, &lo, &hi) - hinc(s, ORA_BZ, k, i - 1, j, th, &lo, &hi)) * idx;
+    else
+      curl = (hinc(s, ORA_BY, k, i, j, th, &lo, &hi) - hinc(s, ORA_BY, k, i - 1, j, th, &lo, &hi)) * idx -
+             (hinc(s, ORA_BX, k, i, j, th, &lo, &hi) - hinc(s, ORA_BX, k, i, j - 1, th, &lo, &hi)) * idy;
+    const double e1 = hinc(s, comp, k, i, j, t1, &lo, &hi), e0 = hinc(s, comp, k, i, j, t0, &lo, &hi);
+    r = curl - (e1 - e0) / dt;
+  } else {
+    const double t0 = n * dt, tm = (n - 0.5) * dt, tq = (n + 0.5) * dt;
+    double curl;
+    if (comp == ORA_BX)
+      curl = (hinc(s, ORA_EZ, k, i, j + 1, t0, &lo, &hi) - hinc(s, ORA_EZ, k, i, j, t0, &lo, &hi)) * idy -
+             (hinc(s, ORA_EY, k + 1, i, j, t0, &lo, &hi) - hinc(s, ORA_EY, k, i, j, t0, &lo, &hi)) * idz;
+    else if (comp == ORA_BY)
+      curl = (hinc(s, ORA_EX, k + 1, i, j, t0, &lo, &hi) - hinc(s, ORA_EX, k, i, j, t0, &lo, &hi)) * idz -
+             (hinc(s, ORA_EZ, k, i + 1, j, t0, &lo, &hi) - hinc(s, ORA_EZ, k, i, j, t0, &lo, &hi)) * idx;
+    else
+      curl = (hinc(s, ORA_EY, k, i + 1, j, t0, &lo, &hi) - hinc(s, ORA_EY, k, i, j, t0, &lo, &hi)) * idx -
+             (hinc(s, ORA_EX, k, i, j + 1, t0, &lo, &hi) - hinc(s, ORA_EX, k, i, j, t0, &lo, &hi)) * idy;
+    const double b1 = hinc(s, comp, k, i, j, tq, &lo, &hi), b0 = hinc(s, comp, k, i, j, tm, &lo, &hi);
+    r = -curl - (b1 - b0) / dt;
+  }
+  if (straddle) *straddle = lo != hi;
+  return lo != hi ? r : 0.0;
+}
+
+static double antenna_source(const ora_state* s, int comp, int64_t n, int k, int i, int j) {
+  return antenna_source_s(s, comp, n, k, i, j, NULL);
+}
+
+/* B -= dt/2 (curl E + M^lev) */
+static void half_B(ora_state* s, int64_t lev) {
   const double h = 0.5 * s->d.dt;
   const double idz = 1.0 / s->p.dz, idx = 1.0 / s->p.dx;
   const double idy = s->p.dims == 3 ? 1.0 / s->p.dy : 0.0;
@@ -389,24 +488,27 @@ void ora_field_half_B(ora_state* s) {
       for (int k = 0; k < zlimit(s, ORA_BX); ++k) { /* Bx at (i, j+1/2, k+1/2) */
         double curl = (fval(s, ORA_EZ, k, i, j + 1) - fval(s, ORA_EZ, k, i, j)) * idy -
                       (fval(s, ORA_EY, k + 1, i, j) - fval(s, ORA_EY, k, i, j)) * idz;
-        s->F[ORA_BX][gidx(s, k, i, j)] -= h * curl;
+        s->F[ORA_BX][gidx(s, k, i, j)] -= h * (curl + antenna_source(s, ORA_BX, lev, k, i, j));
       }
       for (int k = 0; k < zlimit(s, ORA_BY); ++k) { /* By at (i+1/2, j, k+1/2) */
         double curl = (fval(s, ORA_EX, k + 1, i, j) - fval(s, ORA_EX, k, i, j)) * idz -
                       (fval(s, ORA_EZ, k, i + 1, j) - fval(s, ORA_EZ, k, i, j)) * idx;
-        s->F[ORA_BY][gidx(s, k, i, j)] -= h * curl;
+        s->F[ORA_BY][gidx(s, k, i, j)] -= h * (curl + antenna_source(s, ORA_BY, lev, k, i, j));
       }
       for (int k = 0; k < zlimit(s, ORA_BZ); ++k) { /* Bz at (i+1/2, j+1/2, k) */
         double curl = (fval(s, ORA_EY, k, i + 1, j) - fval(s, ORA_EY, k, i, j)) * idx -
                       (fval(s, ORA_EX, k, i, j + 1) - fval(s, ORA_EX, k, i, j)) * idy;
-        s->F[ORA_BZ][gidx(s, k, i, j)] -= h * curl;
+        s->F[ORA_BZ][gidx(s, k, i, j)] -= h * (curl + antenna_source(s, ORA_BZ, lev, k, i, j));
       }
     }
 }
 
-/* E += dt (curl B - J - J_ion); first-order Mur on the tangential E at the
- * open z ends. */
-void ora_field_full_E(ora_state* s) {
+/* half step of B at the current step's time level (the antenna's M^step) */
+void ora_field_half_B(ora_state* s) { half_B(s, s->step); }
+
+/* E += dt (curl B - J - J_ion - J_antenna^{lev+1/2}); first-order Mur on the
+ * tangential E at the open z ends. */
+static void full_E(ora_state* s, int64_t lev) {
   const double dt = s->d.dt;
   const double idz = 1.0 / s->p.dz, idx = 1.0 / s->p.dx;
   const double idy = s->p.dims == 3 ? 1.0 / s->p.dy : 0.0;
@@ -437,20 +539,21 @@ void ora_field_full_E(ora_state* s) {
         double curl = (fval(s, ORA_BZ, k, i, j) - fval(s, ORA_BZ, k, i, j - 1)) * idy -
                       (fval(s, ORA_BY, k, i, j) - fval(s, ORA_BY, k - 1, i, j)) * idz;
         int64_t g = gidx(s, k, i, j);
-        s->F[ORA_EX][g] += dt * (curl - s->F[ORA_JX][g]);
+        s->F[ORA_EX][g] += dt * (curl - s->F[ORA_JX][g] - antenna_source(s, ORA_EX, lev, k, i, j));
       }
       for (int k = 0; k < zlimit(s, ORA_EY); ++k) { /* Ey at (i, j+1/2, k) */
         if (open && (k == 0 || k == nz)) continue;
         double curl = (fval(s, ORA_BX, k, i, j) - fval(s, ORA_BX, k - 1, i, j)) * idz -
                       (fval(s, ORA_BZ, k, i, j) - fval(s, ORA_BZ, k, i - 1, j)) * idx;
         int64_t g = gidx(s, k, i, j);
-        s->F[ORA_EY][g] += dt * (curl - s->F[ORA_JY][g]);
+        s->F[ORA_EY][g] += dt * (curl - s->F[ORA_JY][g] - antenna_source(s, ORA_EY, lev, k, i, j));
       }
       for (int k = 0; k < zlimit(s, ORA_EZ); ++k) { /* Ez at (i, j, k+1/2) */
         double curl = (fval(s, ORA_BY, k, i, j) - fval(s, ORA_BY, k, i - 1, j)) * idx -
                       (fval(s, ORA_BX, k, i, j) - fval(s, ORA_BX, k, i, j - 1)) * idy;
         int64_t g = gidx(s, k, i, j);
-        s->F[ORA_EZ][g] += dt * (curl - s->F[ORA_JZ][g] - jion_z);
+        s->F[ORA_EZ][g] +=
+            dt * (curl - s->F[ORA_JZ][g] - jion_z - antenna_source(s, ORA_EZ, lev, k, i, j));
       }
     }
   if (open) {
@@ -474,12 +577,19 @@ void ora_field_full_E(ora_state* s) {
   }
 }
 
+/* full E step from the current step (the antenna's J^{step+1/2}) */
+void ora_field_full_E(ora_state* s) { full_E(s, s->step); }
+
 /* ------------------------------------------------------------------------ */
 /* laboratory laser: flat phase fronts, Gaussian transverse profile and
- * envelope, travelling along +z; B = z x E. */
+ * envelope, travelling along +z; B = z x E.  Placed in the box, its centre is
+ * at z = zc_boost / D+ at t = 0 (so that at t' = 0 the boosted pulse is
+ * centred at zc_boost); emitted by the antenna, the centre crosses the
+ * antenna plane at t = antenna_t_peak. */
 void ora_laser_lab(const ora_state* s, double z, double t, double x, double y,
                    double E[3], double B[3]) {
-  double zeta = z - s->d.dminus * s->d.zc_boost - t;
+  double zeta = s->p.laser_antenna ? z - s->p.antenna_z_lab - (t - s->p.antenna_t_peak)
+                                   : z - s->d.dminus * s->d.zc_boost - t;
   double Ll = s->d.L_lab;
   double env = exp(-zeta * zeta / (Ll * Ll)) * cos(s->d.k0_lab * zeta);
   double rx = x - 0.5 * s->p.nx * s->p.dx;
@@ -524,6 +634,20 @@ static void init_fields(ora_state* s) {
           double E[3], B[3];
           laser_boosted(s, zp, x, y, E, B);
           double v = comp < 3 ? E[comp] : B[comp - 3];
+          if (s->p.laser_antenna) {
+            /* antenna: the box holds the incident wave above the plane only;
+             * a B point whose first update straddles the plane starts at the
+             * mean of H B_i at t' = -dt/2 and dt/2, so that the first half
+             * step of B lands on H B_i at t' = dt/2 */
+            int lo = 1, hi = 0, st = 0;
+            if (comp >= 3) antenna_source_s(s, comp, 0, k, i, j, &st);
+            if (st) {
+              const double h = 0.5 * s->d.dt;
+              v = 0.5 * (hinc(s, comp, k, i, j, -h, &lo, &hi) + hinc(s, comp, k, i, j, h, &lo, &hi));
+            } else {
+              v = hinc(s, comp, k, i, j, 0.0, &lo, &hi);
+            }
+          }
           s->F[comp][gidx(s, k, i, j)] = v;
         }
   }
@@ -976,9 +1100,9 @@ void ora_step(ora_state* s, int nsteps, double* cont_max) {
       free(rho1);
     }
     if (s->p.filter_passes > 0) ora_filter_current(s);
-    ora_field_half_B(s);
-    ora_field_full_E(s);
-    ora_field_half_B(s);
+    half_B(s, s->step);
+    full_E(s, s->step);
+    half_B(s, s->step + 1);
     /* particle boundary conditions */
     int64_t w = 0;
     for (int64_t p = 0; p < s->np; ++p) {

@@ -65,6 +65,11 @@ typedef struct {
   int n_stations;
   double station_z0, station_dz;
   int station_stride, station_cap;
+  /* laser source: 0 = the pulse is placed in the box at t' = 0; 1 = it is
+   * emitted by an antenna, the lab plane z = antenna_z_lab, whose envelope
+   * peak crosses it at lab time antenna_t_peak */
+  int laser_antenna;
+  double antenna_z_lab, antenna_t_peak;
 } ora_params;
 
 typedef struct {
