@@ -115,6 +115,24 @@ typedef struct {
   double station_z0, station_dz;
   int station_stride;
   int station_cap;
+  /* Laser source (Sec. 2: the laser is injected at a plane fixed in the
+   * laboratory frame and drifting in the boosted frame).  laser_antenna = 0:
+   * the pulse is placed in the box at t' = 0, centred at nz dz / 2.
+   * laser_antenna = 1: the lab plane z = antenna_z_lab (c/omega_p) emits it;
+   * the envelope peak crosses the plane at lab time antenna_t_peak.  In the
+   * boosted frame the plane sits at z'_a = antenna_z_lab / gamma_b - beta_b
+   * t'.  The grid is made to carry the boosted incident wave above the plane
+   * and nothing below: the sources are the residual of the Yee update
+   * applied to H times the incident wave (H = 1 above the plane, at each
+   * point's own staggered z and time), an electric current in the E update
+   * and a magnetic current in the B update, at the points whose update
+   * involves both sides.  They act while 2 dz <= z'_a < (nz - 2) dz; at
+   * t' = 0 the box holds the incident wave above the plane.  In 3D the
+   * flat-phase-front pulse has div E != 0, and the antenna current leaves
+   * the matching charge (reported by the Gauss diagnostic); in 2D with the
+   * polarisation along y it is divergence-free. */
+  int laser_antenna;
+  double antenna_z_lab, antenna_t_peak;
 } pic_lab_params;
 
 typedef struct pic_run pic_run; /* opaque host handle */

@@ -477,8 +477,10 @@ static double antenna_source(const ora_state* s, int comp, int64_t n, int k, int
   return antenna_source_s(s, comp, n, k, i, j, NULL);
 }
 
-/* B -= dt/2 (curl E + M^lev) */
-static void half_B(ora_state* s, int64_t lev) {
+/* B -= dt/2 curl E, and, with_m set, dt M^lev (the antenna's whole
+ * magnetic current of level lev enters the first half step after it, so that
+ * B at integer time is B^{n-1/2} - dt/2 curl E^n, as the gather sees it) */
+static void half_B(ora_state* s, int64_t lev, int with_m) {
   const double h = 0.5 * s->d.dt;
   const double idz = 1.0 / s->p.dz, idx = 1.0 / s->p.dx;
   const double idy = s->p.dims == 3 ? 1.0 / s->p.dy : 0.0;
@@ -488,23 +490,23 @@ static void half_B(ora_state* s, int64_t lev) {
       for (int k = 0; k < zlimit(s, ORA_BX); ++k) { /* Bx at (i, j+1/2, k+1/2) */
         double curl = (fval(s, ORA_EZ, k, i, j + 1) - fval(s, ORA_EZ, k, i, j)) * idy -
                       (fval(s, ORA_EY, k + 1, i, j) - fval(s, ORA_EY, k, i, j)) * idz;
-        s->F[ORA_BX][gidx(s, k, i, j)] -= h * (curl + antenna_source(s, ORA_BX, lev, k, i, j));
+        s->F[ORA_BX][gidx(s, k, i, j)] -= h * curl + (with_m ? 2.0 * h * antenna_source(s, ORA_BX, lev, k, i, j) : 0.0);
       }
       for (int k = 0; k < zlimit(s, ORA_BY); ++k) { /* By at (i+1/2, j, k+1/2) */
         double curl = (fval(s, ORA_EX, k + 1, i, j) - fval(s, ORA_EX, k, i, j)) * idz -
                       (fval(s, ORA_EZ, k, i + 1, j) - fval(s, ORA_EZ, k, i, j)) * idx;
-        s->F[ORA_BY][gidx(s, k, i, j)] -= h * (curl + antenna_source(s, ORA_BY, lev, k, i, j));
+        s->F[ORA_BY][gidx(s, k, i, j)] -= h * curl + (with_m ? 2.0 * h * antenna_source(s, ORA_BY, lev, k, i, j) : 0.0);
       }
       for (int k = 0; k < zlimit(s, ORA_BZ); ++k) { /* Bz at (i+1/2, j+1/2, k) */
         double curl = (fval(s, ORA_EY, k, i + 1, j) - fval(s, ORA_EY, k, i, j)) * idx -
                       (fval(s, ORA_EX, k, i, j + 1) - fval(s, ORA_EX, k, i, j)) * idy;
-        s->F[ORA_BZ][gidx(s, k, i, j)] -= h * (curl + antenna_source(s, ORA_BZ, lev, k, i, j));
+        s->F[ORA_BZ][gidx(s, k, i, j)] -= h * curl + (with_m ? 2.0 * h * antenna_source(s, ORA_BZ, lev, k, i, j) : 0.0);
       }
     }
 }
 
-/* half step of B at the current step's time level (the antenna's M^step) */
-void ora_field_half_B(ora_state* s) { half_B(s, s->step); }
+/* half step of B (Yee only, no antenna source) */
+void ora_field_half_B(ora_state* s) { half_B(s, s->step, 0); }
 
 /* E += dt (curl B - J - J_ion - J_antenna^{lev+1/2}); first-order Mur on the
  * tangential E at the open z ends. */
@@ -636,14 +638,16 @@ static void init_fields(ora_state* s) {
           double v = comp < 3 ? E[comp] : B[comp - 3];
           if (s->p.laser_antenna) {
             /* antenna: the box holds the incident wave above the plane only;
-             * a B point whose first update straddles the plane starts at the
-             * mean of H B_i at t' = -dt/2 and dt/2, so that the first half
+             * a B point whose first update straddles the plane starts at
+             * (H B_i)^{-1/2} - dt/2 curl_h (H E_i)^0, which equals the mean of
+             * H B_i at t' = -dt/2 and dt/2 plus dt/2 M^0, so that the first
              * step of B lands on H B_i at t' = dt/2 */
             int lo = 1, hi = 0, st = 0;
-            if (comp >= 3) antenna_source_s(s, comp, 0, k, i, j, &st);
+            double m0 = 0.0;
+            if (comp >= 3) m0 = antenna_source_s(s, comp, 0, k, i, j, &st);
             if (st) {
               const double h = 0.5 * s->d.dt;
-              v = 0.5 * (hinc(s, comp, k, i, j, -h, &lo, &hi) + hinc(s, comp, k, i, j, h, &lo, &hi));
+              v = 0.5 * (hinc(s, comp, k, i, j, -h, &lo, &hi) + hinc(s, comp, k, i, j, h, &lo, &hi)) + h * m0;
             } else {
               v = hinc(s, comp, k, i, j, 0.0, &lo, &hi);
             }
@@ -1100,9 +1104,9 @@ void ora_step(ora_state* s, int nsteps, double* cont_max) {
       free(rho1);
     }
     if (s->p.filter_passes > 0) ora_filter_current(s);
-    half_B(s, s->step);
+    half_B(s, s->step, 1);
     full_E(s, s->step);
-    half_B(s, s->step + 1);
+    half_B(s, s->step + 1, 0);
     /* particle boundary conditions */
     int64_t w = 0;
     for (int64_t p = 0; p < s->np; ++p) {

@@ -130,8 +130,8 @@ void ora_gather(const ora_state* s, double z, double x, double y,
                 double E[3], double B[3]);
 void ora_deposit(ora_state* s, const double p0[3], const double p1[3], double vy);
 void ora_rho(const ora_state* s, double* rho);        /* electron charge, nodes */
-void ora_field_half_B(ora_state* s);                  /* B -= dt/2 curl E */
-void ora_field_full_E(ora_state* s);                  /* E += dt (curl B - J) */
+void ora_field_half_B(ora_state* s);                  /* B -= dt/2 curl E (no antenna) */
+void ora_field_full_E(ora_state* s);                  /* E += dt (curl B - J - J_antenna) */
 /* Station s's record: *count = samples taken (also those beyond the
  * capacity, which are dropped); times[t] = laboratory time of sample t;
  * data holds, per sample, the six laboratory-frame components

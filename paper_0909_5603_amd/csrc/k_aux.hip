@@ -12,6 +12,7 @@
 // Diagnostics run outside the step loop and accumulate in FP64.
 #include <hip/hip_runtime.h>
 
+#include "antenna.hpp"
 #include "launch.hpp"
 #include "pic_dev.hpp"
 
@@ -59,6 +60,22 @@ __global__ void k_laser(const RunDev* __restrict__ rdp) {
         case 3: v = gb * (B[0] + bb * E[1]); break;
         case 4: v = gb * (B[1] - bb * E[0]); break;
         default: v = B[2]; break;
+      }
+      if (rd.antenna) {
+        // antenna: the incident wave above the plane only; a B point whose
+        // first update straddles the plane starts at (H B_i)^{-1/2} - dt/2
+        // curl_h (H E_i)^0 (the mean of H B_i at t' = -dt/2 and dt/2 plus
+        // dt/2 M^0), so that B^{-1/2} = B^0 + dt/2 curl E^0 is H B_i there
+        int lo = 1, hi = 0;
+        bool st = false;
+        double m0 = 0.0;
+        if (c >= 3) m0 = ant_source(rd, c, 0, k, i, j, &st);
+        if (st) {
+          const double h = 0.5 * rd.dt;
+          v = 0.5 * (ant_hinc(rd, c, k, i, j, -h, lo, hi) + ant_hinc(rd, c, k, i, j, h, lo, hi)) + h * m0;
+        } else {
+          v = ant_hinc(rd, c, k, i, j, 0.0, lo, hi);
+        }
       }
       val = R(v);
     }

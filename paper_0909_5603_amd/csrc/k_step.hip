@@ -1080,19 +1080,25 @@ void launch_particles(int dims, int prec, int pusher, const BatchTable* bt, int 
 }
 
 template <int DIM, typename R>
-static void lf(const BatchTable* bt, int grid, int filter_stages, hipStream_t s) {
+static void lf(const BatchTable* bt, int grid, int filter_stages, long long ant_plane, hipStream_t s) {
+  constexpr int prec = sizeof(R) == 8 ? 1 : 0;
   for (int st = 0; st < filter_stages; ++st)
     hipLaunchKernelGGL((k_filter<DIM, R>), dim3(grid), dim3(256), 0, s, bt, st);
   hipLaunchKernelGGL((k_bhalf<DIM, R>), dim3(grid), dim3(256), 0, s, bt);
+  if (ant_plane > 0) launch_antenna(prec, bt, ant_plane, 0, grid, s);
   hipLaunchKernelGGL((k_efull<DIM, R>), dim3(grid), dim3(256), 0, s, bt);
+  if (ant_plane > 0) launch_antenna(prec, bt, ant_plane, 1, grid, s);
   hipLaunchKernelGGL((k_mur<R>), dim3(grid), dim3(256), 0, s, bt);
 }
 
-void launch_fields(int dims, int prec, const BatchTable* bt, int grid, int filter_stages, hipStream_t s) {
+void launch_fields(int dims, int prec, const BatchTable* bt, int grid, int filter_stages, long long ant_plane,
+                   hipStream_t s) {
   if (dims == 3) {
-    if (prec) lf<3, double>(bt, grid, filter_stages, s); else lf<3, float>(bt, grid, filter_stages, s);
+    if (prec) lf<3, double>(bt, grid, filter_stages, ant_plane, s);
+    else lf<3, float>(bt, grid, filter_stages, ant_plane, s);
   } else {
-    if (prec) lf<2, double>(bt, grid, filter_stages, s); else lf<2, float>(bt, grid, filter_stages, s);
+    if (prec) lf<2, double>(bt, grid, filter_stages, ant_plane, s);
+    else lf<2, float>(bt, grid, filter_stages, ant_plane, s);
   }
 }
 

@@ -14,7 +14,11 @@ int grid_generic(int ncu);
 // one step, split in launches (all read their run set from the batch table)
 void launch_sort_chain(int dims, int prec, const BatchTable* bt, int nruns, int grid, hipStream_t s);
 void launch_particles(int dims, int prec, int pusher, const BatchTable* bt, int grid, hipStream_t s);
-void launch_fields(int dims, int prec, const BatchTable* bt, int grid, int filter_stages, hipStream_t s);
+// ant_plane: transverse points of the largest run with a laser antenna (0: none)
+void launch_fields(int dims, int prec, const BatchTable* bt, int grid, int filter_stages, long long ant_plane,
+                   hipStream_t s);
+// laser antenna sources: phase 0 adds -dt M^n to B^{n+1/2}, phase 1 -dt J^{n+1/2} to E^{n+1}
+void launch_antenna(int prec, const BatchTable* bt, long long max_plane, int phase, int grid, hipStream_t s);
 void launch_advance(const BatchTable* bt, int nruns, hipStream_t s);
 // laboratory-frame stations of every run of the table (before the advance);
 // max_items: station points of the largest station set in the table

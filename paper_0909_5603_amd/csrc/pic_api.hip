@@ -54,6 +54,18 @@ struct Derived {
   // the points one station pass visits (n_stations nxs nys; 0 = none)
   int st_nxs, st_nys;
   long long st_items;
+  long long ant_plane;  // transverse points of an active laser antenna (0: none)
+};
+
+// what a captured step depends on besides the run table: current-filter
+// stages, station points and antenna planes (the most any run of the table needs)
+struct StepShape {
+  int fstages = 0;
+  long long st_items = 0, ant_plane = 0;
+  bool operator==(const StepShape& o) const {
+    return fstages == o.fstages && st_items == o.st_items && ant_plane == o.ant_plane;
+  }
+  bool operator!=(const StepShape& o) const { return !(*this == o); }
 };
 
 struct Layout {
@@ -107,6 +119,9 @@ pic_status derive(const pic_lab_params* p, Derived& d) {
     if (!std::isfinite(p->station_z0) || !std::isfinite(p->station_dz))
       return fail(PIC_EINVAL, "station_z0 and station_dz must be finite");
   }
+  if (p->laser_antenna != 0 && p->laser_antenna != 1) return fail(PIC_EINVAL, "laser_antenna must be 0 or 1");
+  if (p->laser_antenna && (!std::isfinite(p->antenna_z_lab) || !std::isfinite(p->antenna_t_peak)))
+    return fail(PIC_EINVAL, "antenna_z_lab and antenna_t_peak must be finite");
 
   double inv2 = 1.0 / (p->dz * p->dz) + 1.0 / (p->dx * p->dx);
   if (p->dims == 3) inv2 += 1.0 / (p->dy * p->dy);
@@ -168,6 +183,7 @@ pic_status derive(const pic_lab_params* p, Derived& d) {
   d.rsz = p->precision == PIC_FP64 ? sizeof(double) : sizeof(float);
   d.st_nxs = d.st_nys = 0;
   d.st_items = 0;
+  d.ant_plane = (p->laser_antenna && p->a0 > 0) ? d.nperp : 0;
   if (p->n_stations > 0) {
     d.st_nxs = p->nx / p->station_stride;
     d.st_nys = p->dims == 3 ? ny / p->station_stride : 1;
@@ -251,8 +267,7 @@ struct pic_run {
   hipGraphExec_t g1n;  // one single-run step without it
   hipGraphExec_t gB;   // one batched step (this run's batch table), with the sort chain
   hipGraphExec_t gBn;  // the same without it
-  int gB_fstages, gBn_fstages;  // current-filter stages the batched graphs were captured with
-  long long gB_stitems, gBn_stitems;  // and station points
+  StepShape gB_shape, gBn_shape;  // what the batched graphs were captured for
   // host mirror of the device step counter and of the step of the last
   // sort: the sort chain is enqueued only on steps where it has work (the
   // device decides again from its own counters, so the two must agree)
@@ -300,9 +315,15 @@ void host_advance(pic_run* r) {
 }
 
 // enqueue one step for the runs of a batch table
-// st_items: station points of the largest station set in the table (0: no
-// run of the table has stations)
-void enqueue_step(pic_run* r0, const BatchTable* tab, bool cont, bool sort, int fstages, long long st_items) {
+StepShape shape_of(const pic_run* r) {
+  StepShape sh;
+  sh.fstages = r->hrd.filter_stages;
+  sh.st_items = r->d.st_items;
+  sh.ant_plane = r->d.ant_plane;
+  return sh;
+}
+
+void enqueue_step(pic_run* r0, const BatchTable* tab, bool cont, bool sort, const StepShape& sh) {
   const int dims = r0->p.dims, prec = r0->p.precision;
   hipStream_t s = r0->stream;
   if (sort) launch_sort_chain(dims, prec, tab, MAX_BATCH, r0->ggen, s);
@@ -315,17 +336,17 @@ void enqueue_step(pic_run* r0, const BatchTable* tab, bool cont, bool sort, int 
     launch_rho(dims, prec, r0->drd, at<double>(r0, r0->L.rho_b), r0->d.npts, r0->d.capacity, 1, s);
     launch_cont_post(dims, prec, r0->drd, r0->d.npts, r0->d.capacity, s);
   }
-  launch_fields(dims, prec, tab, r0->ggen, fstages, s);
+  launch_fields(dims, prec, tab, r0->ggen, sh.fstages, sh.ant_plane, s);
   // E[fbuf] = E^n and B[fbuf] = B^{n-1/2} are intact until the advance flips fbuf
-  if (st_items > 0) launch_stations(prec, tab, st_items, r0->ggen, s);
+  if (sh.st_items > 0) launch_stations(prec, tab, sh.st_items, r0->ggen, s);
   launch_advance(tab, MAX_BATCH, s);
 }
 
-pic_status capture(pic_run* r, const BatchTable* tab, bool cont, bool sort, int fstages,
-                   long long st_items, hipGraphExec_t* out) {
+pic_status capture(pic_run* r, const BatchTable* tab, bool cont, bool sort, const StepShape& sh,
+                   hipGraphExec_t* out) {
   hipGraph_t g = nullptr;
   HIPCHK(hipStreamBeginCapture(r->stream, hipStreamCaptureModeThreadLocal));
-  enqueue_step(r, tab, cont, sort, fstages, st_items);
+  enqueue_step(r, tab, cont, sort, sh);
   hipError_t e = hipStreamEndCapture(r->stream, &g);
   if (e != hipSuccess) return fail(PIC_EHIP, "graph capture: %s", hipGetErrorString(e));
   e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
@@ -448,8 +469,7 @@ pic_status pic_init_boosted(const pic_lab_params* p, void* dev_buf, size_t bytes
   r->g1n = nullptr;
   r->gB = nullptr;
   r->gBn = nullptr;
-  r->gB_fstages = r->gBn_fstages = 0;
-  r->gB_stitems = r->gBn_stitems = 0;
+  r->gB_shape = r->gBn_shape = StepShape();
   // the initial sort below runs at step 0
   r->hstep = 0;
   r->hlast_sort = 0;
@@ -529,6 +549,9 @@ pic_status pic_init_boosted(const pic_lab_params* p, void* dev_buf, size_t bytes
   }
   h.ftmp[0] = at<double>(r, L.ftmp[0]);
   h.ftmp[1] = at<double>(r, L.ftmp[1]);
+  h.antenna = (r->p.laser_antenna && r->p.a0 > 0) ? 1 : 0;
+  h.ant_z_lab = r->p.antenna_z_lab;
+  h.ant_t_peak = r->p.antenna_t_peak;
   h.n_stations = r->p.n_stations;
   if (h.n_stations > 0) {
     h.st_stride = r->p.station_stride;
@@ -615,12 +638,12 @@ pic_status pic_step(pic_run* r, int nsteps) {
     if (graph) {
       hipGraphExec_t& g = sort ? r->g1 : r->g1n;
       if (!g) {
-        pic_status st = capture(r, r->dtab1, cont, sort, r->hrd.filter_stages, r->d.st_items, &g);
+        pic_status st = capture(r, r->dtab1, cont, sort, shape_of(r), &g);
         if (st != PIC_OK) return st;
       }
       HIPCHK(hipGraphLaunch(g, r->stream));
     } else {
-      enqueue_step(r, r->dtab1, cont, sort, r->hrd.filter_stages, r->d.st_items);
+      enqueue_step(r, r->dtab1, cont, sort, shape_of(r));
     }
     host_advance(r);
   }
@@ -652,7 +675,7 @@ pic_status pic_step_timed(pic_run* r, int nsteps, double ms[4]) {
       (void)hipEventRecord(e[1], s);
       launch_particles(dims, prec, r->p.pusher, r->dtab1, r->gpart, s);
       (void)hipEventRecord(e[2], s);
-      launch_fields(dims, prec, r->dtab1, r->ggen, r->hrd.filter_stages, s);
+      launch_fields(dims, prec, r->dtab1, r->ggen, r->hrd.filter_stages, r->d.ant_plane, s);
       if (r->d.st_items > 0) launch_stations(prec, r->dtab1, r->d.st_items, r->ggen, s);
       launch_advance(r->dtab1, MAX_BATCH, s);
       (void)hipEventRecord(e[3], s);
@@ -709,31 +732,30 @@ pic_status pic_step_batch(pic_run* const* runs, const int* nsteps, int n) {
                             r0->stream));
     }
     bool sort = false;
-    int fst = 0;           // filter stages: the most any run of the batch needs
-    long long sti = 0;     // station points: the most any run of the batch has
+    StepShape sh;  // the most any run of the batch needs
     for (pic_run* q : act) {
       sort = sort || host_sort_due(q);
-      fst = std::max(fst, q->hrd.filter_stages);
-      sti = std::max(sti, q->d.st_items);
+      const StepShape qs = shape_of(q);
+      sh.fstages = std::max(sh.fstages, qs.fstages);
+      sh.st_items = std::max(sh.st_items, qs.st_items);
+      sh.ant_plane = std::max(sh.ant_plane, qs.ant_plane);
     }
     if (r0->use_graph && r0->stream != nullptr) {
       hipGraphExec_t& g = sort ? r0->gB : r0->gBn;
-      int& gst = sort ? r0->gB_fstages : r0->gBn_fstages;
-      long long& gsi = sort ? r0->gB_stitems : r0->gBn_stitems;
-      if (g && (gst != fst || gsi != sti)) {
+      StepShape& gsh = sort ? r0->gB_shape : r0->gBn_shape;
+      if (g && gsh != sh) {
         HIPCHK(hipStreamSynchronize(r0->stream));
         (void)hipGraphExecDestroy(g);
         g = nullptr;
       }
       if (!g) {
-        pic_status st = capture(r0, r0->dtabB, false, sort, fst, sti, &g);
+        pic_status st = capture(r0, r0->dtabB, false, sort, sh, &g);
         if (st != PIC_OK) return st;
-        gst = fst;
-        gsi = sti;
+        gsh = sh;
       }
       HIPCHK(hipGraphLaunch(g, r0->stream));
     } else {
-      enqueue_step(r0, r0->dtabB, false, sort, fst, sti);
+      enqueue_step(r0, r0->dtabB, false, sort, sh);
     }
     for (pic_run* q : act) host_advance(q);
   }

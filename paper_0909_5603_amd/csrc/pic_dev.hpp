@@ -136,6 +136,9 @@ struct RunDev {
   PIC_G double* st_time;      // [station][st_cap] lab times
   PIC_G double* st_data;      // [station][st_cap][6][st_nys][st_nxs] lab fields
   PIC_G long long* st_count;  // [station] samples taken
+  // laser antenna: on/off, lab z of the plane, lab time of the envelope peak
+  int antenna, pad_a;
+  double ant_z_lab, ant_t_peak;
 };
 
 // a run descriptor as the kernels see it (read-only, constant address space)

@@ -47,6 +47,8 @@ class pic_lab_params(ctypes.Structure):
         ("filter_compensate", ctypes.c_int), ("n_stations", ctypes.c_int),
         ("station_z0", ctypes.c_double), ("station_dz", ctypes.c_double),
         ("station_stride", ctypes.c_int), ("station_cap", ctypes.c_int),
+        ("laser_antenna", ctypes.c_int), ("antenna_z_lab", ctypes.c_double),
+        ("antenna_t_peak", ctypes.c_double),
     ]
 
 
@@ -142,6 +144,9 @@ def make_params(cfg: dict, precision: str = "fp32", continuity: bool = False) ->
     p.n_stations = int(cfg.get("n_stations", 0))
     p.station_z0 = float(cfg.get("station_z0", 0.0)); p.station_dz = float(cfg.get("station_dz", 0.0))
     p.station_stride = int(cfg.get("station_stride", 1)); p.station_cap = int(cfg.get("station_cap", 0))
+    p.laser_antenna = int(cfg.get("laser_antenna", 0))
+    p.antenna_z_lab = float(cfg.get("antenna_z_lab", 0.0))
+    p.antenna_t_peak = float(cfg.get("antenna_t_peak", 0.0))
     return p
 
 

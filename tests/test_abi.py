@@ -51,6 +51,8 @@ def test_state_bytes_scale_with_the_workload(pic):
     (dict(gamma_boost=0.5), -1), (dict(ppc=-1), -1), (dict(sort_every=0), -1),
     (dict(nz=4000), -1), (dict(pol_axis=3), -1), (dict(filter_passes=17), -1),
     (dict(filter_passes=-1), -1), (dict(filter_passes=1, filter_compensate=2), -1),
+    (dict(laser_antenna=2), -1), (dict(laser_antenna=1, antenna_z_lab=float("nan")), -1),
+    (dict(laser_antenna=1, antenna_t_peak=float("inf")), -1),
 ])
 def test_invalid_parameters(pic, over, status):
     cfg = workloads.config("c1", **over)

@@ -72,3 +72,37 @@ def test_fp32_split_push_cancellation_and_gamma_drift():
     uo, _ = oracle.push_many(u, E, np.tile(B, (n, 1)), cell + off, workloads.PUSH_DT, nsteps)
     rel = np.linalg.norm(ug - uo, axis=1) / np.linalg.norm(uo, axis=1)
     assert rel.max() < 1e-4
+
+
+@pytest.mark.parametrize("prec", [pic.PIC_FP64, pic.PIC_FP32_SPLIT])
+def test_boris_error_grows_with_gamma_vay_exact(prec):
+    """The paper's motivating comparison on the GPU kernels: a particle
+    co-moving with a beam of rest-frame field E_rest = 1 sees E_x = gamma,
+    B_y = beta gamma; the net transverse kick over one step is
+    -dt E_x / gamma^2.  The modified pusher reproduces it; the Boris pusher's
+    relative error grows like gamma^2 (~1.25e-3 gamma^2 at dt = 0.1).
+    FP32 storage: E and v x B cancel to 1/gamma^2, so the split path is held
+    to a bound of 2^-24 gamma^2 at gamma = 100 only."""
+    n, dt = 256, workloads.PUSH_DT
+    gammas = [1e2, 1e3, 1e4] if prec == pic.PIC_FP64 else [1e2]
+    errs = {}
+    for g in gammas:
+        b = np.sqrt(1.0 - 1.0 / g**2)
+        u = np.zeros((n, 3))
+        u[:, 2] = g * b
+        Ex = np.full(n, g)
+        cell = np.zeros((n, 3), dtype=np.int32)
+        off = np.full((n, 3), 0.5)
+        phys = -dt * g / g**2
+        for pusher in (pic.PIC_VAY, pic.PIC_BORIS):
+            ug, _ = _gpu_push(prec, pusher, u, Ex, [0.0, b * g, 0.0], cell, off, 1, dt)
+            errs[(g, pusher)] = np.abs(ug[:, 0] - phys).max() / abs(phys)
+    for g in gammas:
+        ev, eb = errs[(g, pic.PIC_VAY)], errs[(g, pic.PIC_BORIS)]
+        print(f"\ngamma {g:.0e}: relative kick error Vay {ev:.2e}, Boris {eb:.2e}")
+        if prec == pic.PIC_FP64:
+            assert ev < 1e-6
+            assert eb == pytest.approx(1.25e-3 * g**2, rel=0.05)
+        else:
+            assert ev < 2.0**-24 * g**2 * 4
+            assert eb > 1e3 * ev
