@@ -64,7 +64,8 @@ enum {
 typedef struct {
   int dims;              /* 2: (z,x) with three velocity components; 3: (z,x,y) */
   int nz, nx, ny;        /* boosted-frame cells; ny ignored in 2D.  nx, ny must be
-                            multiples of the transverse tile (2D: 16; 3D: 8 x 4) */
+                            multiples of the transverse tile (2D: 16; 3D: 8 x 8 in
+                            split precision, 8 x 4 in FP64) */
   double dz, dx, dy;     /* cell sizes in c/omega_p */
   double cfl;            /* dt = cfl / sqrt(sum_d 1/d^2); must be in (0, 1) */
   int ppc;               /* electrons per cell (>= 0) */

@@ -34,9 +34,9 @@ __device__ __forceinline__ void pending(RunC& rd, const PIC_G Counters& c, long 
   nnew = rd.ppc > 0 ? ncol * rd.nperp * rd.ppc : 0;
 }
 
-template <int DIM>
+template <int DIM, typename R>
 __device__ __forceinline__ int tile_of(RunC& rd, int c) {
-  using T = Tile<DIM>;
+  using T = Tile<DIM, R>;
   const int tz = cell_k(c) >> T::LZ;
   const int tx = cell_i(c) >> T::LX;
   const int ty = DIM == 3 ? (cell_j(c) >> T::LY) : 0;
@@ -158,7 +158,7 @@ __global__ __launch_bounds__(256) void k_inject(const BatchTable* __restrict__ b
 }
 
 // ------------------------------------------------------------------ count
-template <int DIM>
+template <int DIM, typename R>
 __global__ __launch_bounds__(256) void k_count(const BatchTable* __restrict__ bt) {
   const XcdSplit xs(bt->partblk);
   for (long long w = xs.beg; w < xs.end; w += xs.stride) {
@@ -178,7 +178,7 @@ __global__ __launch_bounds__(256) void k_count(const BatchTable* __restrict__ bt
       int cc = -1;
       if (q < total) cc = cellp[q];
       const bool act = cc >= 0;
-      const int key = act ? tile_of<DIM>(rd, cc) : 0;
+      const int key = act ? tile_of<DIM, R>(rd, cc) : 0;
       wave_agg_count(rd.tile_count, key, act);
     }
   }
@@ -272,7 +272,7 @@ __global__ __launch_bounds__(256) void k_scatter(const BatchTable* __restrict__ 
         v[5] = fptr<R>(rd.u[src][2])[q];
         id = rd.pid[src][q];
       }
-      const int key = act ? tile_of<DIM>(rd, cc) : 0;
+      const int key = act ? tile_of<DIM, R>(rd, cc) : 0;
       const int slot = wave_agg_add(rd.tile_cursor, key, act);
       if (act) {
         rd.cell[dst][slot] = cc;
@@ -308,7 +308,7 @@ __global__ void k_commit(const BatchTable* __restrict__ bt) {
 template <int DIM, typename R>
 static void chain(const BatchTable* bt, int nruns, int grid, hipStream_t s) {
   hipLaunchKernelGGL((k_inject<R>), dim3(grid), dim3(256), 0, s, bt);
-  hipLaunchKernelGGL((k_count<DIM>), dim3(grid), dim3(256), 0, s, bt);
+  hipLaunchKernelGGL((k_count<DIM, R>), dim3(grid), dim3(256), 0, s, bt);
   hipLaunchKernelGGL(k_scan, dim3(nruns), dim3(1024), 0, s, bt);
   hipLaunchKernelGGL((k_scatter<DIM, R>), dim3(grid), dim3(256), 0, s, bt);
   hipLaunchKernelGGL(k_commit, dim3((nruns + 63) / 64), dim3(64), 0, s, bt);

@@ -377,13 +377,16 @@ __device__ __forceinline__ int new_cell(RunC& rd, int k, int i, int j, const int
   return cell_pack(k1, i1, j1) | (dead ? (int)DEAD : 0);
 }
 
-// Occupancy of the 3D particle kernel.  Its LDS window (about 77 KiB in
-// split precision, 115 KiB in FP64) admits two workgroups per CU (one in
-// FP64), so the workgroup is 512 threads and the registers are capped at
-// 512 / waves-per-SIMD: 16 resident waves per CU in split precision, 8 in
-// FP64.
+// Occupancy of the 3D particle kernel.  Its LDS window (111 KiB in split
+// precision, 115 KiB in FP64) admits one workgroup per CU, so the workgroup
+// is 1024 threads in split precision (16 resident waves per CU, registers
+// capped at 128) and 512 in FP64 (8 waves; the FP64 state needs the
+// registers).  The larger split-precision tile (8x8x8 cells, 8192 particles
+// at 16 per cell) spreads the window load and the current flush over twice
+// the particles of an 8x8x4 tile: 11.0 against 11.9 ms per step at
+// 512x256x256.
 #ifndef PIC_PBLOCK3
-#define PIC_PBLOCK3 512
+#define PIC_PBLOCK3 1024
 #endif
 #ifndef PIC_WPE3
 #define PIC_WPE3 4
@@ -406,7 +409,7 @@ struct PWaves {
 template <int DIM, typename R, int BLOCK, int PUSHER>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(PWaves<DIM, R, BLOCK>::value)))
 void k_particles(const BatchTable* __restrict__ bt) {
-  using T = Tile<DIM>;
+  using T = Tile<DIM, R>;
   constexpr int WZM = T::WZ, WXM = T::WX, WYM = T::WY;
   constexpr int WV = WZM * WXM * WYM;
   constexpr int SY = (DIM == 3) ? WZM * WXM : 0;  // LDS stride of y
@@ -742,7 +745,7 @@ void k_particles(const BatchTable* __restrict__ bt) {
 // queue (empty in the steady boosted-frame flow).
 template <int DIM, typename R, int PUSHER>
 __global__ __launch_bounds__(256) void k_particles_hbm(const BatchTable* __restrict__ bt) {
-  using T = Tile<DIM>;
+  using T = Tile<DIM, R>;
   for (int r = 0; r < bt->n; ++r) {
     RunC& rd = *bt->run[r];
     const PIC_G Counters& ctr = *rd.ctr;
@@ -1047,9 +1050,10 @@ int grid_particles(int dims, int prec, int ncu) {
   const size_t per_cell = 6 * sizeof(float) * (prec ? 2 : 1) + 3 * sizeof(long long);
   size_t lds;
   if (dims == 3)
-    lds = per_cell * Tile<3>::WZ * Tile<3>::WX * Tile<3>::WY;
+    lds = prec ? per_cell * Tile<3, double>::WZ * Tile<3, double>::WX * Tile<3, double>::WY
+               : per_cell * Tile<3, float>::WZ * Tile<3, float>::WX * Tile<3, float>::WY;
   else
-    lds = per_cell * Tile<2>::WZ * Tile<2>::WX;
+    lds = per_cell * Tile<2, float>::WZ * Tile<2, float>::WX;
   int per_cu = (int)((160 * 1024) / (lds + 1024));
   if (per_cu < 1) per_cu = 1;
   if (per_cu > 8) per_cu = 8;

@@ -86,15 +86,16 @@ constexpr size_t NOPT = (size_t)-1;
 pic_status derive(const pic_lab_params* p, Derived& d) {
   if (!p) return fail(PIC_EINVAL, "params is NULL");
   if (p->dims != 2 && p->dims != 3) return fail(PIC_EINVAL, "dims must be 2 or 3");
-  const int TZ = p->dims == 3 ? Tile<3>::TZ : Tile<2>::TZ;
-  const int TX = p->dims == 3 ? Tile<3>::TX : Tile<2>::TX;
-  const int TY = p->dims == 3 ? Tile<3>::TY : 1;
+  const bool f64 = p->precision == PIC_FP64;
+  const int TZ = p->dims == 3 ? (f64 ? Tile<3, double>::TZ : Tile<3, float>::TZ) : Tile<2, float>::TZ;
+  const int TX = p->dims == 3 ? (f64 ? Tile<3, double>::TX : Tile<3, float>::TX) : Tile<2, float>::TX;
+  const int TY = p->dims == 3 ? (f64 ? Tile<3, double>::TY : Tile<3, float>::TY) : 1;
   const int ny = p->dims == 3 ? p->ny : 1;
   if (p->nz < 8) return fail(PIC_EINVAL, "nz must be >= 8");
   if (p->nx < TX || p->nx % TX || p->nx > (1 << IBITS))
     return fail(PIC_EINVAL, "nx must be a multiple of %d in [%d, %d]", TX, TX, 1 << IBITS);
-  if (p->dims == 3 && (ny < 4 || ny % TY || ny > (1 << JBITS)))
-    return fail(PIC_EINVAL, "ny must be a multiple of %d in [4, %d]", TY, 1 << JBITS);
+  if (p->dims == 3 && (ny < TY || ny % TY || ny > (1 << JBITS)))
+    return fail(PIC_EINVAL, "ny must be a multiple of %d in [%d, %d]", TY, TY, 1 << JBITS);
   if (!(p->dz > 0) || !(p->dx > 0) || (p->dims == 3 && !(p->dy > 0)))
     return fail(PIC_EINVAL, "cell sizes must be positive");
   if (!(p->cfl > 0) || !(p->cfl < 1)) return fail(PIC_ECFL, "cfl must be in (0, 1)");

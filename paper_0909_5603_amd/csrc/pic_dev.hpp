@@ -42,19 +42,15 @@ constexpr unsigned DEAD = 0x80000000u;
 // window spans the tile's particle bounding box widened by one cell below
 // and two above (gather and deposit stencils): W = extent + 3, plus one cell
 // of slack for the fractional drift of the plasma between two sorts in z.
-template <int DIM> struct Tile;
-#ifndef PIC_WZ3
-#define PIC_WZ3 14
-#endif
-#ifndef PIC_WY3
-#define PIC_WY3 9
-#endif
-template <> struct Tile<3> {
-  static constexpr int LZ = 3, LX = 3, LY = 2;
+// 3D split precision: 8x8x8 cells, a 14x13x13 window of 111 KiB (one
+// 1024-thread workgroup per CU); 3D FP64: 8x8x4 cells, 14x13x9, 115 KiB.
+template <int DIM, typename R> struct Tile;
+template <typename R> struct Tile<3, R> {
+  static constexpr int LZ = 3, LX = 3, LY = sizeof(R) == 4 ? 3 : 2;
   static constexpr int TZ = 1 << LZ, TX = 1 << LX, TY = 1 << LY;
-  static constexpr int WZ = PIC_WZ3, WX = TX + 5, WY = PIC_WY3;
+  static constexpr int WZ = TZ + 6, WX = TX + 5, WY = TY + 5;
 };
-template <> struct Tile<2> {
+template <typename R> struct Tile<2, R> {
   static constexpr int LZ = 4, LX = 4, LY = 0;
   static constexpr int TZ = 1 << LZ, TX = 1 << LX, TY = 1;
   static constexpr int WZ = TZ + 6, WX = TX + 5, WY = 1;
