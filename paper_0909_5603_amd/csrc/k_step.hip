@@ -62,10 +62,17 @@ __device__ __forceinline__ R interp(const W1<R>* w, F&& fetch) {
   if constexpr (DIM == 3) {
     const R y0 = sy ? w[2].h0 : w[2].n0, y1 = sy ? w[2].h1 : w[2].n1;
     const int oy = sy ? w[2].hb : 0;
-    const R a = z0 * fetch(C, oz, ox, oy) + z1 * fetch(C, oz + 1, ox, oy);
-    const R b = z0 * fetch(C, oz, ox + 1, oy) + z1 * fetch(C, oz + 1, ox + 1, oy);
-    const R c = z0 * fetch(C, oz, ox, oy + 1) + z1 * fetch(C, oz + 1, ox, oy + 1);
-    const R d = z0 * fetch(C, oz, ox + 1, oy + 1) + z1 * fetch(C, oz + 1, ox + 1, oy + 1);
+    // the 8 loads first, then the arithmetic: keeps four LDS reads in
+    // flight instead of waiting on each one
+    R v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v[q] = fetch(C, oz + (q & 1), ox + ((q >> 1) & 1), oy + (q >> 2));
+    __builtin_amdgcn_sched_group_barrier(0x100, 8, 0);  // DS reads
+    __builtin_amdgcn_sched_group_barrier(0x002, 14, 0);  // then VALU
+    const R a = z0 * v[0] + z1 * v[1];
+    const R b = z0 * v[2] + z1 * v[3];
+    const R c = z0 * v[4] + z1 * v[5];
+    const R d = z0 * v[6] + z1 * v[7];
     return y0 * (x0 * a + x1 * b) + y1 * (x0 * c + x1 * d);
   } else {
     const R a = z0 * fetch(C, oz, ox, 0) + z1 * fetch(C, oz + 1, ox, 0);
@@ -302,22 +309,17 @@ struct PConst {
 
 template <int DIM, typename R>
 __device__ __forceinline__ PConst<R> pconst(RunC& rd) {
+  // computed once on the host (the FP64 divisions cost ~100 VALU
+  // instructions per tile and wavefront when done here)
   PConst<R> K;
-  K.eps = R(-0.5 * rd.dt);
-  K.cdz = R(rd.dt / rd.dz);
-  K.cdx = R(rd.dt / rd.dx);
-  K.cdy = R(rd.dt / rd.dy);
-  const double S = rd.jscale;
-  if (DIM == 3) {
-    K.cz = R(S * rd.weight / (rd.dx * rd.dy * rd.dt));
-    K.cx = R(S * rd.weight / (rd.dz * rd.dy * rd.dt));
-    K.cy = R(S * rd.weight / (rd.dz * rd.dx * rd.dt));
-  } else {
-    K.cz = R(S * rd.weight / (rd.dx * rd.dt));
-    K.cx = R(S * rd.weight / (rd.dz * rd.dt));
-    K.cy = R(0);
-  }
-  K.cyv = R(-S * rd.weight / (rd.dz * rd.dx));
+  K.eps = R(rd.pk[0]);
+  K.cdz = R(rd.pk[1]);
+  K.cdx = R(rd.pk[2]);
+  K.cdy = R(rd.pk[3]);
+  K.cz = R(rd.pk[4]);
+  K.cx = R(rd.pk[5]);
+  K.cy = R(rd.pk[6]);
+  K.cyv = R(rd.pk[7]);
   return K;
 }
 

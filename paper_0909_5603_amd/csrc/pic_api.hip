@@ -532,6 +532,23 @@ pic_status pic_init_boosted(const pic_lab_params* p, void* dev_buf, size_t bytes
   // current in 64-bit fixed point (scale chosen in derive)
   h.jscale = d.jscale;
   h.jinv = 1.0 / h.jscale;
+  {
+    const double S = h.jscale, w = h.weight, dt = h.dt, dz = h.dz, dx = h.dx, dy = h.dy;
+    h.pk[0] = -0.5 * dt;
+    h.pk[1] = dt / dz;
+    h.pk[2] = dt / dx;
+    h.pk[3] = dt / dy;
+    if (h.dims == 3) {
+      h.pk[4] = S * w / (dx * dy * dt);
+      h.pk[5] = S * w / (dz * dy * dt);
+      h.pk[6] = S * w / (dz * dx * dt);
+    } else {
+      h.pk[4] = S * w / (dx * dt);
+      h.pk[5] = S * w / (dz * dt);
+      h.pk[6] = 0.0;
+    }
+    h.pk[7] = -S * w / (dz * dx);
+  }
   h.seed = r->p.seed;
   const Layout& L = r->L;
   for (int b = 0; b < 2; ++b)

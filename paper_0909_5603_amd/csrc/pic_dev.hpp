@@ -101,6 +101,9 @@ struct RunDev {
   double beta_b, gamma_b, dminus, dplus, weight, jion_z, rho_ion, u_th;
   double k0_lab, E0_lab, L_lab, zc_boost, waist;
   double jscale, jinv;  // current stored as int64 = round(J * jscale)
+  // particle-update constants: -dt/2 (q/m = -1), dt/dz, dt/dx, dt/dy, and the
+  // current coefficients (times jscale) of Jz, Jx, Jy and the 2D out-of-plane Jy
+  double pk[8];
   unsigned long long seed;
   // arrays (device addresses inside the caller's buffer); element type is
   // float (split-precision path) or double (FP64 path)
