@@ -211,6 +211,35 @@ def filter_cost(cfg, pic, torch, fields_ms_plain, nsteps=10, passes=1, compensat
             "filter_ms_per_step": fms, "filter_GBs": fbytes / (fms * 1e-3) / 1e9 if fms > 0 else None}
 
 
+def lab_io_cost(cfg, pic, torch, fields_ms_plain, nsteps=10, n_stations=32, stride=4):
+    """The same workload with the laboratory-frame input and output switched
+    on: the laser emitted by an antenna plane (starting at 3/4 of the box,
+    the pulse crossing it during the timed steps) and n_stations lab-fixed
+    stations spread over the box, every stride-th transverse node.  Returns
+    the field-stage time (where both run) against the plain run's."""
+    probe = pic.Run(dict(cfg, ppc=0, nz=16, nx=8, ny=8), "fp32")  # derived quantities only
+    d = probe.derived
+    probe.close()
+    g, b = d["gamma_b"], d["beta_b"]
+    Lz = cfg["nz"] * cfg["dz"]
+    Za = g * 0.75 * Lz
+    lcfg = dict(cfg, laser_antenna=1, antenna_z_lab=Za,
+                antenna_t_peak=b * Za + 8.0 * d["dt"] / g,  # the envelope peak after 8 steps
+                n_stations=n_stations, station_z0=g * 0.05 * Lz, station_dz=g * 0.9 * Lz / n_stations,
+                station_stride=stride, station_cap=64)
+    run = pic.Run(lcfg, "fp32")
+    run.step(2)
+    run.synchronize()
+    ms = pic.pic_step_timed(run.handle, nsteps)
+    nys, nxs = pic.station_shape(run.params)
+    run.close()
+    del run
+    torch.cuda.empty_cache()
+    return {"n_stations": n_stations, "station_points": n_stations * nys * nxs, "antenna": True,
+            "ms_per_step_events": ms["step"], "fields_ms_per_step": ms["fields"],
+            "lab_io_ms_per_step": ms["fields"] - fields_ms_plain}
+
+
 def serving(pic, torch, n_requests, budget_gib, chunk):
     from paper_0909_5603_amd import serve, workloads
 
@@ -253,6 +282,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-filter", action="store_true",
                     help="skip the run with the low-pass current filter")
+    ap.add_argument("--no-lab-io", action="store_true",
+                    help="skip the run with the laser antenna and lab-frame stations")
     ap.add_argument("--timing-steps", type=int, default=20)
     ap.add_argument("--serve-requests", type=int, default=64)
     ap.add_argument("--profile", action="store_true",
@@ -321,6 +352,11 @@ def main():
         line["filter"] = fc
         log(f"[filter] {fc['stages']} stages: {fc['filter_ms_per_step']:.3f} ms/step "
             f"(step {fc['ms_per_step_events']:.3f} ms)")
+    if not args.no_lab_io:
+        lc = lab_io_cost(cfg, pic, torch, ms["fields"])
+        line["lab_io"] = lc
+        log(f"[lab io] antenna + {lc['n_stations']} stations: {lc['lab_io_ms_per_step']:.3f} ms/step "
+            f"(step {lc['ms_per_step_events']:.3f} ms)")
     if not args.no_serving:
         res = serving(pic, torch, args.serve_requests, budget_gib=96.0, chunk=25)
         line["serving"] = res
