@@ -744,21 +744,28 @@ void k_particles(const BatchTable* __restrict__ bt) {
 
 // Particles whose stencil left their tile's window: gather from and deposit
 // into HBM directly, then widen the tile's bounding box.  Normally a tiny
-// queue (empty in the steady boosted-frame flow).
+// queue (empty in the steady boosted-frame flow).  Each workgroup serves one
+// run of the batch (the grid holds at least four workgroups per run), so a
+// launch with empty queues costs one chain of dependent loads, not one per
+// run.
 template <int DIM, typename R, int PUSHER>
 __global__ __launch_bounds__(256) void k_particles_hbm(const BatchTable* __restrict__ bt) {
   using T = Tile<DIM, R>;
-  for (int r = 0; r < bt->n; ++r) {
+  const int nr = bt->n;
+  const int parts = (int)gridDim.x / nr;
+  if ((int)blockIdx.x >= parts * nr) return;
+  {
+    const int r = (int)blockIdx.x % nr, part = (int)blockIdx.x / nr;
     RunC& rd = *bt->run[r];
     const PIC_G Counters& ctr = *rd.ctr;
     const long long n = min((long long)ctr.n_slowq, rd.capacity);
-    if (n == 0) continue;
+    if (n == 0) return;
     const int pb = ctr.pbuf, fb = ctr.fbuf, bb = ctr.bbuf;
     const Arr3<R> Eg = PIC_ARR3(R, rd.E[fb]);
     const Arr3<R> Bg = PIC_ARR3(R, rd.B[fb]);
     const PConst<R> K = pconst<DIM, R>(rd);
-    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n;
-         e += (long long)gridDim.x * blockDim.x) {
+    for (long long e = (long long)part * blockDim.x + threadIdx.x; e < n;
+         e += (long long)parts * blockDim.x) {
       const int p = rd.slowq[e];
       const int c = rd.cell[pb][p];
       const int k = cell_k(c), i = cell_i(c), j = DIM == 3 ? cell_j(c) : 0;
@@ -1014,17 +1021,21 @@ __global__ __launch_bounds__(256) void k_filter(const BatchTable* __restrict__ b
 
 template <typename R>
 __global__ __launch_bounds__(256) void k_mur(const BatchTable* __restrict__ bt) {
-  // 2 nperp boundary columns per open run, visited run by run (a batch
-  // holds few runs, so the outer loop is short and uniform)
-  for (int r = 0; r < bt->n; ++r) {
+  // 2 nperp boundary columns per open run; each workgroup serves one run of
+  // the batch (the grid holds at least eight workgroups per run)
+  const int nr = bt->n;
+  const int parts = (int)gridDim.x / nr;
+  if ((int)blockIdx.x >= parts * nr) return;
+  {
+    const int r = (int)blockIdx.x % nr, part = (int)blockIdx.x / nr;
     RunC& rd = *bt->run[r];
-    if (!rd.open) continue;
+    if (!rd.open) return;
     const unsigned nperp = (unsigned)rd.nperp, nzf = (unsigned)rd.nzf;
     const int fb = rd.ctr->fbuf;
     const Arr3<R> E = PIC_ARR3(R, rd.E[fb]);
     const Arr3<R> En = PIC_ARR3(R, rd.E[fb ^ 1]);
     const R cm = R((rd.dt - rd.dz) / (rd.dt + rd.dz));
-    for (unsigned q = blockIdx.x * 256u + threadIdx.x; q < 2u * nperp; q += gridDim.x * 256u) {
+    for (unsigned q = (unsigned)part * 256u + threadIdx.x; q < 2u * nperp; q += (unsigned)parts * 256u) {
       const unsigned side = q >= nperp ? 1u : 0u;
       const unsigned col = (q - side * nperp) * nzf;
       const unsigned kb = side ? (unsigned)rd.nz : 0u, ki = side ? (unsigned)rd.nz - 1u : 1u;
@@ -1063,12 +1074,15 @@ int grid_particles(int dims, int prec, int ncu) {
   return (g + 7) & ~7;
 }
 
-int grid_generic(int ncu) { return ncu * 8; }
+// (at least one workgroup per run of a full batch: k_mur serves one run per
+// workgroup)
+int grid_generic(int ncu) { return ncu * 8 > MAX_BATCH ? ncu * 8 : MAX_BATCH; }
 
 template <int DIM, typename R>
 static void lp(int pusher, const BatchTable* bt, int grid, hipStream_t s) {
   constexpr int B = PBlock<DIM, R>::value;
   if (pusher == 1) {
+    static_assert(1024 >= 4 * MAX_BATCH, "the out-of-window kernel serves one run per workgroup");
     hipLaunchKernelGGL((k_particles<DIM, R, B, 1>), dim3(grid), dim3(B), 0, s, bt);
     hipLaunchKernelGGL((k_particles_hbm<DIM, R, 1>), dim3(1024), dim3(256), 0, s, bt);
   } else {
