@@ -315,7 +315,7 @@ void host_advance(pic_run* r) {
   ++r->hstep;
 }
 
-// enqueue one step for the runs of a batch table
+// what one run needs of a captured step
 StepShape shape_of(const pic_run* r) {
   StepShape sh;
   sh.fstages = r->hrd.filter_stages;
@@ -324,6 +324,7 @@ StepShape shape_of(const pic_run* r) {
   return sh;
 }
 
+// enqueue one step for the runs of a batch table
 void enqueue_step(pic_run* r0, const BatchTable* tab, bool cont, bool sort, const StepShape& sh) {
   const int dims = r0->p.dims, prec = r0->p.precision;
   hipStream_t s = r0->stream;
