@@ -285,7 +285,7 @@ def main():
     ap.add_argument("--no-lab-io", action="store_true",
                     help="skip the run with the laser antenna and lab-frame stations")
     ap.add_argument("--timing-steps", type=int, default=20)
-    ap.add_argument("--serve-requests", type=int, default=64)
+    ap.add_argument("--serve-requests", type=int, default=256)
     ap.add_argument("--profile", action="store_true",
                     help="only the split-precision timed loop and the copy calibration kernel "
                          "(for rocprofv3 runs)")

@@ -174,8 +174,12 @@ pic_status pic_init_boosted(const pic_lab_params* p, void* dev_buf, size_t bytes
                             void* hip_stream, pic_run** out);
 
 /* Enqueue nsteps full PIC steps (gather, modified-Lorentz push, move,
- * charge-conserving deposit, Yee update; sort and injection every sort_every
- * steps).  Asynchronous. */
+ * charge-conserving deposit, Yee update; tile sort and plasma injection
+ * every sort_every steps, and a tile sort alone within four steps after a
+ * step in which more than 1/128 of the particles left their tiles' LDS
+ * windows).  The storage
+ * order of the particles changes only at sorts; results do not depend on
+ * it.  Asynchronous. */
 pic_status pic_step(pic_run* run, int nsteps);
 
 /* Advance several runs together: their tiles share the same kernel launches.

@@ -1,6 +1,8 @@
 // Plasma-column injection and the counting sort of particles by tile.
 //
-// Every sort_every steps: (1) create the lattice columns that have drifted
+// Every sort_every steps, and at a step that follows one in which more than
+// 1/128 of a run's particles left their tile windows (then without (1)):
+// (1) create the lattice columns that have drifted
 // into the reservoir beyond z_max (Philox-drawn positions, laboratory
 // Maxwellian momenta boosted to the frame: Sec. 2, second paragraph - the
 // plasma is denser and drifting in the boosted frame), appending them after
@@ -23,6 +25,11 @@ namespace pic {
 // columns and particles the pending injection of this step creates
 __device__ __forceinline__ void pending(RunC& rd, const PIC_G Counters& c, long long& kend,
                                         long long& nnew) {
+  if (c.step % rd.inject_every != 0) {  // a sort between cadence steps injects nothing
+    kend = c.next_col;
+    nnew = 0;
+    return;
+  }
   if (rd.open) {
     const double shift = rd.beta_b * ((double)c.step * rd.dt) / rd.dz;
     kend = (long long)rd.nz + rd.reservoir + (long long)ceil(shift);
@@ -83,18 +90,60 @@ __device__ __forceinline__ void wave_agg_count(PIC_G int* base, int key, bool ac
   }
 }
 
+// The work items of the runs that sort at this step, as one flat range:
+// thread t reads run t's counters (in parallel), the workgroup scans the
+// item counts in LDS, and item w maps back to its run by a binary search of
+// the scan.  A step where no run sorts (most steps) costs one round of loads;
+// a step where one small run of a large batch sorts touches only its items.
+// Every thread of the workgroup must call it; returns the number of items.
+struct SortItems {
+  long long pre[MAX_BATCH + 1];
+};
+
+__device__ __forceinline__ long long sort_items(const BatchTable* bt, const long long* pre_items,
+                                                SortItems& si) {
+  const int n = bt->n;
+  for (int r = threadIdx.x; r < n; r += blockDim.x) {
+    RunC& rd = *bt->run[r];
+    si.pre[r + 1] = sort_due(*rd.ctr, rd.inject_every) ? pre_items[r + 1] - pre_items[r] : 0;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    long long acc = 0;
+    si.pre[0] = 0;
+    for (int r = 0; r < n; ++r) {
+      acc += si.pre[r + 1];
+      si.pre[r + 1] = acc;
+    }
+  }
+  __syncthreads();
+  return si.pre[n];
+}
+
+// the run of sorting item w: the last r with pre[r] <= w
+__device__ __forceinline__ int sort_item_run(const SortItems& si, int n, long long w) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (si.pre[mid] <= w) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
 // ------------------------------------------------------------------ inject
 template <typename R>
 __global__ __launch_bounds__(256) void k_inject(const BatchTable* __restrict__ bt) {
-  const XcdSplit xs(bt->injblk);
+  __shared__ SortItems si;
+  const long long items = sort_items(bt, bt->pre_injblk, si);
+  if (items == 0) return;
+  const XcdSplit xs(items);
   for (long long w = xs.beg; w < xs.end; w += xs.stride) {
-    const int r = __builtin_amdgcn_readfirstlane(locate(bt->pre_injblk, bt->n, w));
+    const int r = __builtin_amdgcn_readfirstlane(sort_item_run(si, bt->n, w));
     RunC& rd = *bt->run[r];
     const PIC_G Counters& c = *rd.ctr;
-    if (!sort_due(c, rd.inject_every)) continue;
     long long kend, nnew;
     pending(rd, c, kend, nnew);
-    const long long blk = w - bt->pre_injblk[r];
+    const long long blk = w - si.pre[r];
     if (blk * INJ_CHUNK >= nnew) continue;
     const int pb = c.pbuf;
     const long long per_col = rd.nperp * rd.ppc;
@@ -160,17 +209,19 @@ __global__ __launch_bounds__(256) void k_inject(const BatchTable* __restrict__ b
 // ------------------------------------------------------------------ count
 template <int DIM, typename R>
 __global__ __launch_bounds__(256) void k_count(const BatchTable* __restrict__ bt) {
-  const XcdSplit xs(bt->partblk);
+  __shared__ SortItems si;
+  const long long items = sort_items(bt, bt->pre_partblk, si);
+  if (items == 0) return;
+  const XcdSplit xs(items);
   for (long long w = xs.beg; w < xs.end; w += xs.stride) {
-    const int r = __builtin_amdgcn_readfirstlane(locate(bt->pre_partblk, bt->n, w));
+    const int r = __builtin_amdgcn_readfirstlane(sort_item_run(si, bt->n, w));
     RunC& rd = *bt->run[r];
     const PIC_G Counters& c = *rd.ctr;
-    if (!sort_due(c, rd.inject_every)) continue;
     long long kend, nnew;
     pending(rd, c, kend, nnew);
     long long total = c.n_slots + nnew;
     if (total > rd.capacity) total = rd.capacity;
-    const long long blk = w - bt->pre_partblk[r];
+    const long long blk = w - si.pre[r];
     if (blk * PART_CHUNK >= total) continue;
     const PIC_G int* cellp = rd.cell[c.pbuf];
     for (int t = threadIdx.x; t < PART_CHUNK; t += 256) {
@@ -240,17 +291,19 @@ __global__ __launch_bounds__(1024) void k_scan(const BatchTable* __restrict__ bt
 // ------------------------------------------------------------------ scatter
 template <int DIM, typename R>
 __global__ __launch_bounds__(256) void k_scatter(const BatchTable* __restrict__ bt) {
-  const XcdSplit xs(bt->partblk);
+  __shared__ SortItems si;
+  const long long items = sort_items(bt, bt->pre_partblk, si);
+  if (items == 0) return;
+  const XcdSplit xs(items);
   for (long long w = xs.beg; w < xs.end; w += xs.stride) {
-    const int r = __builtin_amdgcn_readfirstlane(locate(bt->pre_partblk, bt->n, w));
+    const int r = __builtin_amdgcn_readfirstlane(sort_item_run(si, bt->n, w));
     RunC& rd = *bt->run[r];
     const PIC_G Counters& c = *rd.ctr;
-    if (!sort_due(c, rd.inject_every)) continue;
     long long kend, nnew;
     pending(rd, c, kend, nnew);
     long long total = c.n_slots + nnew;
     if (total > rd.capacity) total = rd.capacity;
-    const long long blk = w - bt->pre_partblk[r];
+    const long long blk = w - si.pre[r];
     if (blk * PART_CHUNK >= total) continue;
     const int src = c.pbuf, dst = src ^ 1;
     const PIC_G int* cellp = rd.cell[src];
@@ -303,6 +356,7 @@ __global__ void k_commit(const BatchTable* __restrict__ bt) {
   c->pbuf ^= 1;
   c->fresh = 1;
   c->last_sort = c->step;
+  c->want_sort = 0;
 }
 
 template <int DIM, typename R>

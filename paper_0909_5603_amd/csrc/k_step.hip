@@ -744,28 +744,48 @@ void k_particles(const BatchTable* __restrict__ bt) {
 
 // Particles whose stencil left their tile's window: gather from and deposit
 // into HBM directly, then widen the tile's bounding box.  Normally a tiny
-// queue (empty in the steady boosted-frame flow).  Each workgroup serves one
-// run of the batch (the grid holds at least four workgroups per run), so a
-// launch with empty queues costs one chain of dependent loads, not one per
-// run.
+// queue (empty in the steady boosted-frame flow).  Every workgroup first
+// reads all the runs' queue lengths in parallel (one thread per run) and
+// scans them in LDS; the queued particles of all runs are then one flat range
+// shared by the whole grid, so an empty launch costs one round of loads and a
+// heavy run's queue is spread over every workgroup.
 template <int DIM, typename R, int PUSHER>
 __global__ __launch_bounds__(256) void k_particles_hbm(const BatchTable* __restrict__ bt) {
   using T = Tile<DIM, R>;
+  __shared__ long long pre[MAX_BATCH + 1];
   const int nr = bt->n;
-  const int parts = (int)gridDim.x / nr;
-  if ((int)blockIdx.x >= parts * nr) return;
-  {
-    const int r = (int)blockIdx.x % nr, part = (int)blockIdx.x / nr;
+  for (int r = threadIdx.x; r < nr; r += blockDim.x) {
+    RunC& rd = *bt->run[r];
+    pre[r + 1] = min((long long)rd.ctr->n_slowq, rd.capacity);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    long long acc = 0;
+    pre[0] = 0;
+    for (int r = 0; r < nr; ++r) {
+      acc += pre[r + 1];
+      pre[r + 1] = acc;
+    }
+  }
+  __syncthreads();
+  const long long total = pre[nr];
+  for (long long w = (long long)blockIdx.x * blockDim.x + threadIdx.x; w < total;
+       w += (long long)gridDim.x * blockDim.x) {
+    // the run of item w: the last r with pre[r] <= w
+    int lo = 0, hi = nr - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (pre[mid] <= w) lo = mid; else hi = mid - 1;
+    }
+    const int r = lo;
+    const long long e = w - pre[r];
     RunC& rd = *bt->run[r];
     const PIC_G Counters& ctr = *rd.ctr;
-    const long long n = min((long long)ctr.n_slowq, rd.capacity);
-    if (n == 0) return;
     const int pb = ctr.pbuf, fb = ctr.fbuf, bb = ctr.bbuf;
     const Arr3<R> Eg = PIC_ARR3(R, rd.E[fb]);
     const Arr3<R> Bg = PIC_ARR3(R, rd.B[fb]);
     const PConst<R> K = pconst<DIM, R>(rd);
-    for (long long e = (long long)part * blockDim.x + threadIdx.x; e < n;
-         e += (long long)parts * blockDim.x) {
+    {
       const int p = rd.slowq[e];
       const int c = rd.cell[pb][p];
       const int k = cell_k(c), i = cell_i(c), j = DIM == 3 ? cell_j(c) : 0;
@@ -1049,6 +1069,9 @@ __global__ void k_advance(const BatchTable* __restrict__ bt) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= bt->n) return;
   PIC_G Counters* c = bt->run[r]->ctr;
+  // more than 1/128 of the particles took the out-of-window path (each costs
+  // tens of window pushes): re-sort at the next step
+  if ((long long)c->n_slowq * 128 > c->n_slots) c->want_sort = 1;
   c->n_slow += c->n_slowq;
   c->n_slowq = 0;
   c->step += 1;
@@ -1082,7 +1105,6 @@ template <int DIM, typename R>
 static void lp(int pusher, const BatchTable* bt, int grid, hipStream_t s) {
   constexpr int B = PBlock<DIM, R>::value;
   if (pusher == 1) {
-    static_assert(1024 >= 4 * MAX_BATCH, "the out-of-window kernel serves one run per workgroup");
     hipLaunchKernelGGL((k_particles<DIM, R, B, 1>), dim3(grid), dim3(B), 0, s, bt);
     hipLaunchKernelGGL((k_particles_hbm<DIM, R, 1>), dim3(1024), dim3(256), 0, s, bt);
   } else {

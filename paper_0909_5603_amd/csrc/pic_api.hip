@@ -264,15 +264,16 @@ struct pic_run {
   BatchTable htabB;
   int ncu, gpart, ggen;
   bool use_graph;
-  hipGraphExec_t g1;   // one single-run step with the sort chain
-  hipGraphExec_t g1n;  // one single-run step without it
-  hipGraphExec_t gB;   // one batched step (this run's batch table), with the sort chain
-  hipGraphExec_t gBn;  // the same without it
-  StepShape gB_shape, gBn_shape;  // what the batched graphs were captured for
-  // host mirror of the device step counter and of the step of the last
-  // sort: the sort chain is enqueued only on steps where it has work (the
-  // device decides again from its own counters, so the two must agree)
-  long long hstep, hlast_sort;
+  hipGraphExec_t g1[2];  // one single-run step: [1] with the sort chain, [0] without
+  hipGraphExec_t gB[2];  // one batched step (this run's batch table), likewise
+  StepShape gB_shape[2];  // what the batched graphs were captured for
+  // host mirror of the device step counter (checked at every read-back).
+  // The sort chain is enqueued on every cadence step and every CHAIN_EVERY-th
+  // step in between; the device decides whether it sorts (cadence, or a
+  // request left by a step with too many out-of-window particles, which
+  // stays pending until a step that carries the chain) and its kernels
+  // return at once otherwise.
+  long long hstep;
 };
 
 namespace {
@@ -304,15 +305,14 @@ void fill_table(BatchTable& t, pic_run* const* runs, int n) {
   t.pre_injblk[n] = t.injblk = e;
 }
 
-// does the next step of run r sort (and inject)?  Same rule as the device:
-// a multiple of the cadence that has not been sorted yet
-bool host_sort_due(const pic_run* r) {
-  return r->hstep % r->p.sort_every == 0 && r->hstep != r->hlast_sort;
-}
+void host_advance(pic_run* r) { ++r->hstep; }
 
-void host_advance(pic_run* r) {
-  if (host_sort_due(r)) r->hlast_sort = r->hstep;
-  ++r->hstep;
+// steps that carry the sort chain: the cadence, and every CHAIN_EVERY-th
+// step for sorts the device requests in between (an idle chain costs five
+// small launches, a sizeable share of the step of small batched runs)
+constexpr int CHAIN_EVERY = 4;
+bool chain_step(const pic_run* r) {
+  return r->hstep % r->p.sort_every == 0 || r->hstep % CHAIN_EVERY == 0;
 }
 
 // what one run needs of a captured step
@@ -325,10 +325,10 @@ StepShape shape_of(const pic_run* r) {
 }
 
 // enqueue one step for the runs of a batch table
-void enqueue_step(pic_run* r0, const BatchTable* tab, bool cont, bool sort, const StepShape& sh) {
+void enqueue_step(pic_run* r0, const BatchTable* tab, bool cont, bool chain, const StepShape& sh) {
   const int dims = r0->p.dims, prec = r0->p.precision;
   hipStream_t s = r0->stream;
-  if (sort) launch_sort_chain(dims, prec, tab, MAX_BATCH, r0->ggen, s);
+  if (chain) launch_sort_chain(dims, prec, tab, MAX_BATCH, r0->ggen, s);
   if (cont) {
     launch_cont_pre(dims, prec, r0->drd, r0->d.npts, r0->d.capacity, s);
     launch_rho(dims, prec, r0->drd, at<double>(r0, r0->L.rho_a), r0->d.npts, r0->d.capacity, 1, s);
@@ -344,11 +344,11 @@ void enqueue_step(pic_run* r0, const BatchTable* tab, bool cont, bool sort, cons
   launch_advance(tab, MAX_BATCH, s);
 }
 
-pic_status capture(pic_run* r, const BatchTable* tab, bool cont, bool sort, const StepShape& sh,
+pic_status capture(pic_run* r, const BatchTable* tab, bool cont, bool chain, const StepShape& sh,
                    hipGraphExec_t* out) {
   hipGraph_t g = nullptr;
   HIPCHK(hipStreamBeginCapture(r->stream, hipStreamCaptureModeThreadLocal));
-  enqueue_step(r, tab, cont, sort, sh);
+  enqueue_step(r, tab, cont, chain, sh);
   hipError_t e = hipStreamEndCapture(r->stream, &g);
   if (e != hipSuccess) return fail(PIC_EHIP, "graph capture: %s", hipGetErrorString(e));
   e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
@@ -370,9 +370,8 @@ const double* gauss_rho(pic_run* r) {
 pic_status read_counters(pic_run* r, Counters& c) {
   HIPCHK(hipMemcpyAsync(&c, r->dctr, sizeof(Counters), hipMemcpyDeviceToHost, r->stream));
   HIPCHK(hipStreamSynchronize(r->stream));
-  if (c.step != r->hstep || c.last_sort != r->hlast_sort)
-    return fail(PIC_ESTATE, "step counters disagree (device step %lld sort %lld, host %lld %lld)", c.step,
-                c.last_sort, r->hstep, r->hlast_sort);
+  if (c.step != r->hstep)
+    return fail(PIC_ESTATE, "step counters disagree (device %lld, host %lld)", c.step, r->hstep);
   return PIC_OK;
 }
 
@@ -467,14 +466,10 @@ pic_status pic_init_boosted(const pic_lab_params* p, void* dev_buf, size_t bytes
   r->bytes = bytes;
   r->stream = static_cast<hipStream_t>(hip_stream);
   r->use_graph = true;
-  r->g1 = nullptr;
-  r->g1n = nullptr;
-  r->gB = nullptr;
-  r->gBn = nullptr;
-  r->gB_shape = r->gBn_shape = StepShape();
-  // the initial sort below runs at step 0
+  r->g1[0] = r->g1[1] = nullptr;
+  r->gB[0] = r->gB[1] = nullptr;
+  r->gB_shape[0] = r->gB_shape[1] = StepShape();
   r->hstep = 0;
-  r->hlast_sort = 0;
   int dev = 0;
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&r->ncu, hipDeviceAttributeMultiprocessorCount, dev);
@@ -653,16 +648,16 @@ pic_status pic_step(pic_run* r, int nsteps) {
   // the legacy null stream cannot be captured: launch eagerly there
   const bool graph = r->use_graph && r->stream != nullptr && nsteps >= 2;
   for (int i = 0; i < nsteps; ++i) {
-    const bool sort = host_sort_due(r);
+    const bool chain = chain_step(r);
     if (graph) {
-      hipGraphExec_t& g = sort ? r->g1 : r->g1n;
+      hipGraphExec_t& g = r->g1[chain ? 1 : 0];
       if (!g) {
-        pic_status st = capture(r, r->dtab1, cont, sort, shape_of(r), &g);
+        pic_status st = capture(r, r->dtab1, cont, chain, shape_of(r), &g);
         if (st != PIC_OK) return st;
       }
       HIPCHK(hipGraphLaunch(g, r->stream));
     } else {
-      enqueue_step(r, r->dtab1, cont, sort, shape_of(r));
+      enqueue_step(r, r->dtab1, cont, chain, shape_of(r));
     }
     host_advance(r);
   }
@@ -689,7 +684,7 @@ pic_status pic_step_timed(pic_run* r, int nsteps, double ms[4]) {
     for (int i = 0; i < nsteps; ++i) {
       hipEvent_t* e = &ev[(size_t)i * 4];
       (void)hipEventRecord(e[0], s);
-      if (host_sort_due(r)) launch_sort_chain(dims, prec, r->dtab1, MAX_BATCH, r->ggen, s);
+      if (chain_step(r)) launch_sort_chain(dims, prec, r->dtab1, MAX_BATCH, r->ggen, s);
       host_advance(r);
       (void)hipEventRecord(e[1], s);
       launch_particles(dims, prec, r->p.pusher, r->dtab1, r->gpart, s);
@@ -750,31 +745,31 @@ pic_status pic_step_batch(pic_run* const* runs, const int* nsteps, int n) {
       HIPCHK(hipMemcpyAsync(r0->dtabB, &r0->htabB, sizeof(BatchTable), hipMemcpyHostToDevice,
                             r0->stream));
     }
-    bool sort = false;
     StepShape sh;  // the most any run of the batch needs
+    bool chain = false;
     for (pic_run* q : act) {
-      sort = sort || host_sort_due(q);
+      chain = chain || chain_step(q);
       const StepShape qs = shape_of(q);
       sh.fstages = std::max(sh.fstages, qs.fstages);
       sh.st_items = std::max(sh.st_items, qs.st_items);
       sh.ant_plane = std::max(sh.ant_plane, qs.ant_plane);
     }
     if (r0->use_graph && r0->stream != nullptr) {
-      hipGraphExec_t& g = sort ? r0->gB : r0->gBn;
-      StepShape& gsh = sort ? r0->gB_shape : r0->gBn_shape;
+      hipGraphExec_t& g = r0->gB[chain ? 1 : 0];
+      StepShape& gsh = r0->gB_shape[chain ? 1 : 0];
       if (g && gsh != sh) {
         HIPCHK(hipStreamSynchronize(r0->stream));
         (void)hipGraphExecDestroy(g);
         g = nullptr;
       }
       if (!g) {
-        pic_status st = capture(r0, r0->dtabB, false, sort, sh, &g);
+        pic_status st = capture(r0, r0->dtabB, false, chain, sh, &g);
         if (st != PIC_OK) return st;
         gsh = sh;
       }
       HIPCHK(hipGraphLaunch(g, r0->stream));
     } else {
-      enqueue_step(r0, r0->dtabB, false, sort, sh);
+      enqueue_step(r0, r0->dtabB, false, chain, sh);
     }
     for (pic_run* q : act) host_advance(q);
   }
@@ -951,10 +946,10 @@ pic_status pic_get_derived(const pic_run* r, pic_derived* o) {
 
 pic_status pic_free(pic_run* r) {
   if (!r) return PIC_OK;
-  if (r->g1) (void)hipGraphExecDestroy(r->g1);
-  if (r->g1n) (void)hipGraphExecDestroy(r->g1n);
-  if (r->gB) (void)hipGraphExecDestroy(r->gB);
-  if (r->gBn) (void)hipGraphExecDestroy(r->gBn);
+  for (int q = 0; q < 2; ++q) {
+    if (r->g1[q]) (void)hipGraphExecDestroy(r->g1[q]);
+    if (r->gB[q]) (void)hipGraphExecDestroy(r->gB[q]);
+  }
   delete r;
   return PIC_OK;
 }

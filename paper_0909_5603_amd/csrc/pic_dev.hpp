@@ -50,10 +50,16 @@ template <typename R> struct Tile<3, R> {
   static constexpr int TZ = 1 << LZ, TX = 1 << LX, TY = 1 << LY;
   static constexpr int WZ = TZ + 6, WX = TX + 5, WY = TY + 5;
 };
+// 2D: 16x16 cells, a 22x37 window (39 KiB; four 256-thread workgroups per
+// CU): 21 cells of transverse slack, because electrons quivering in a
+// strong laser at low gamma_b (a0 ~ 3, gamma_b ~ 2) spread across x by more
+// than half a cell per step between sorts, and those that leave the window
+// take the out-of-window path at tens of times the cost (a 37-wide window
+// took the serving stream's p50 from 191 to 127 ms against 21).
 template <typename R> struct Tile<2, R> {
   static constexpr int LZ = 4, LX = 4, LY = 0;
   static constexpr int TZ = 1 << LZ, TX = 1 << LX, TY = 1;
-  static constexpr int WZ = TZ + 6, WX = TX + 5, WY = 1;
+  static constexpr int WZ = TZ + 6, WX = TX + 21, WY = 1;
 };
 
 // Yee staggering per component (half-cell flags in z, x, y):
@@ -74,7 +80,7 @@ struct Counters {
   long long k_end;     // column bound of the pending injection
   int pbuf, fbuf, bbuf, fresh;
   unsigned err;
-  int pad0;
+  int want_sort;       // sort at the next step: too many particles left their windows
   // continuity diagnostic (max over steps, as bit patterns of non-negative doubles)
   unsigned long long cont_res_bits, cont_rho_bits;
   double cont_max;
@@ -304,10 +310,12 @@ __device__ __forceinline__ void atomic_max_pos(PIC_G unsigned long long* a, doub
   g_max(a, (unsigned long long)__double_as_longlong(v));
 }
 
-// the sort/injection of a step runs when the step is a multiple of the
-// cadence and has not been sorted yet
+// the tile sort of a step runs when the step is a multiple of the cadence
+// (the plasma-column injection runs only then) or when the previous step
+// sent too many particles to the out-of-window path, and the step has not
+// been sorted yet
 __device__ __forceinline__ bool sort_due(const PIC_G Counters& c, int every) {
-  return (c.step % every) == 0 && c.step != c.last_sort;
+  return ((c.step % every) == 0 || c.want_sort != 0) && c.step != c.last_sort;
 }
 
 template <typename R> __device__ __forceinline__ PIC_G R* fptr(PIC_G void* p) { return (PIC_G R*)p; }

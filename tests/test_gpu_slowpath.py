@@ -2,9 +2,10 @@
 oracle.
 
 A hot plasma (lab thermal spread 0.5, boosted at gamma_b = 2, periodic box,
-no re-sorting) spreads the particles of a tile over more cells than its LDS
-window holds within a few steps; those particles are gathered from and
-deposited into HBM directly.  The results must not depend on which path a
+sort cadence 50 steps) spreads the particles of a tile over more cells than
+its LDS window holds within a few steps; those particles are gathered from
+and deposited into HBM directly, and the run re-sorts its tiles at the next
+step.  The results must not depend on which path a
 particle took: FP64 matches the oracle to rounding, split precision keeps
 the momentum and continuity bounds, and the diagnostics report that the
 path was taken."""
@@ -65,7 +66,9 @@ def test_out_of_window_particles_match_oracle(prec):
     n = st.particles()["id"].size
     print(f"\n{prec}: {slow} out-of-window pushes over 8 steps ({slow / (8 * n):.1%}), "
           f"max du/u {worst:.3e}, max dx {perr:.3e}, continuity {cont:.2e}")
-    assert slow > 0.01 * 8 * n
+    # the path is taken (re-sorting after a step with more than 1/128 of the
+    # particles out of their windows keeps it from growing further)
+    assert slow > 0
     if prec == "fp64":
         assert worst < 1e-10 and perr < 1e-10
     else:
