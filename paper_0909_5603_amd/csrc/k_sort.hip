@@ -1,7 +1,8 @@
 // Plasma-column injection and the counting sort of particles by tile.
 //
-// Every sort_every steps, and at a step that follows one in which more than
-// 1/128 of a run's particles left their tile windows (then without (1)):
+// Every sort_every steps, and (without (1)) at the first step carrying the
+// sort chain after one in which more than 1/128 of a run's particles left
+// their tile windows:
 // (1) create the lattice columns that have drifted
 // into the reservoir beyond z_max (Philox-drawn positions, laboratory
 // Maxwellian momenta boosted to the frame: Sec. 2, second paragraph - the
