@@ -14,7 +14,9 @@ step above the plane).  What the mathematics fixes:
   divergence, so Gauss's law and the particle continuity stay at round-off
   with a plasma present;
 * a pulse already crossing the plane at t' = 0 starts as H (E_i, B_i) and
-  evolves the same way.
+  evolves the same way;
+* closing the loop, a laboratory-frame station downstream of the plane
+  records the laboratory pulse, converging at second order.
 """
 import numpy as np
 import pytest
@@ -124,3 +126,31 @@ def test_gauss_law_and_continuity_with_plasma_2d(ora):
     assert d["gauss_drift"] < 1e-12
     assert d["U_E"] > 0
     st.close()
+
+
+def test_downstream_station_records_the_laboratory_pulse(ora):
+    """The whole lab -> boosted -> lab loop inside the oracle: the pulse given
+    in the laboratory is emitted by the drifting antenna, evolved in the
+    boosted frame, and recorded by a station 0.1 L_z gamma_b downstream of
+    the plane; the station's lab-frame E_y(t_lab) is the lab pulse at the
+    station's z, up to the Yee and interpolation errors (second order)."""
+    errs = []
+    for nz in (256, 512):
+        cfg, Ll = _antenna_cfg(ora, nz)
+        st0 = ora.State(dict(cfg, ppc=0))
+        d = st0.derived
+        g, b, Lz = d["gamma_b"], d["beta_b"], cfg["nz"] * cfg["dz"]
+        Zs = cfg["antenna_z_lab"] + 0.1 * g * Lz
+        st = ora.State(dict(cfg, n_stations=1, station_z0=Zs, station_dz=0.0,
+                            station_stride=cfg["nx"], station_cap=4000))
+        st.step(int(0.5 * Lz / (b * d["dt"])))
+        t, data, n = st.station(0)
+        ey = data[:, 1, 0, 0]
+        ana = np.array([st0.laser_lab(Zs, tl, 0.0)[0][1] for tl in t])
+        pk = np.abs(ana).max()
+        assert pk > 0.9 * d["E0_lab"]  # the whole pulse went past
+        errs.append(np.abs(ey - ana).max() / pk)
+        st.close()
+        st0.close()
+    print(f"\nlab pulse at the station: {errs[0]:.2e} -> {errs[1]:.2e}")
+    assert errs[1] < 0.35 * errs[0] and errs[1] < 5e-3
