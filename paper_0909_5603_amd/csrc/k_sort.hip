@@ -132,6 +132,21 @@ __device__ __forceinline__ int sort_item_run(const SortItems& si, int n, long lo
 }
 
 // ------------------------------------------------------------------ inject
+// The b-th transverse cell (i, j) of an nx x ny plane enumerated tile by
+// tile: rows of tiles of tx x ty cells, the tiles of a row left to right,
+// the cells of a tile row by row; the last row and column of tiles may be
+// narrower.
+__device__ __forceinline__ void blocked_cell(long long b, int nx, int ny, int tx, int ty, int& i, int& j) {
+  const int tyi = (int)(b / ((long long)ty * nx));
+  long long r = b - (long long)tyi * ty * nx;
+  const int wy = min(ty, ny - tyi * ty);
+  const int txi = (int)(r / ((long long)tx * wy));
+  r -= (long long)txi * tx * wy;
+  const int wx = min(tx, nx - txi * tx);
+  j = tyi * ty + (int)(r / wx);
+  i = txi * tx + (int)(r % wx);
+}
+
 template <typename R>
 __global__ __launch_bounds__(256) void k_inject(const BatchTable* __restrict__ bt) {
   __shared__ SortItems si;
@@ -157,14 +172,19 @@ __global__ __launch_bounds__(256) void k_inject(const BatchTable* __restrict__ b
         g_or(&rd.ctr->err, 2u);
         break;
       }
-      // slot outermost within a column: consecutive new particles lie in
-      // consecutive cells, so the lanes of a wavefront deposit to different
-      // LDS addresses; the lattice id does not depend on this order
+      // slot outermost within a column, the transverse cells in tile-blocked
+      // order: a wavefront creates one lattice slot of the cells of one
+      // tile's transverse plane, which the sort keeps together, so the lanes
+      // of a wavefront of the step kernel lie in different cells and their
+      // LDS current atomics never share an address.  The lattice id does
+      // not depend on this order.
       const long long K = c.next_col + q / per_col;
       const long long rem = q % per_col;
       const long long sl = rem / rd.nperp;
-      const long long cperp = rem % rd.nperp;
-      const int i = (int)(cperp % rd.nx), j = (int)(cperp / rd.nx);
+      int i, j;
+      blocked_cell(rem % rd.nperp, rd.nx, rd.dims == 3 ? rd.ny : 1, rd.dims == 3 ? Tile<3, R>::TX : Tile<2, R>::TX,
+                   rd.dims == 3 ? Tile<3, R>::TY : 1, i, j);
+      const long long cperp = (long long)j * rd.nx + i;
       const uint64_t L = (uint64_t)((K * rd.nperp + cperp) * rd.ppc + sl);
       uint64_t a[4] = {L, 0, 0, 0}, b[4] = {L, 1, 0, 0};
       philox4x64_10(a, rd.seed, 0);
