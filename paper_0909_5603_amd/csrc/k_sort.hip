@@ -173,11 +173,13 @@ __global__ __launch_bounds__(256) void k_inject(const BatchTable* __restrict__ b
         break;
       }
       // slot outermost within a column, the transverse cells in tile-blocked
-      // order: a wavefront creates one lattice slot of the cells of one
-      // tile's transverse plane, which the sort keeps together, so the lanes
-      // of a wavefront of the step kernel lie in different cells and their
-      // LDS current atomics never share an address.  The lattice id does
-      // not depend on this order.
+      // order: in split precision a wavefront creates one lattice slot of
+      // the 8x8 cells of one tile's transverse plane, which the sort keeps
+      // together, so the lanes of a wavefront of the step kernel start in 64
+      // different cells and their LDS current atomics do not share
+      // addresses (an FP64 tile plane has 8x4 cells, so there a wavefront
+      // holds two slots of it).  The lattice id does not depend on this
+      // order.
       const long long K = c.next_col + q / per_col;
       const long long rem = q % per_col;
       const long long sl = rem / rd.nperp;
