@@ -23,6 +23,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -240,6 +242,46 @@ def lab_io_cost(cfg, pic, torch, fields_ms_plain, nsteps=10, n_stations=32, stri
             "lab_io_ms_per_step": ms["fields"] - fields_ms_plain}
 
 
+def pusher_cost(pic, torch, nsteps=50, n=1 << 27):
+    """Pusher microbenchmark: 2^27 particles, each in its own crossed field
+    (E = -v x B, gamma log-uniform in [1e2, 1e6]), one launch per step, the
+    modified Lorentz-force (Vay) and Boris pushers in split precision and
+    FP64, timed with HIP events on the launching stream.  Bytes per push:
+    the position and momentum state read and written plus E, counting the
+    int32 cells (76 B in split precision, 128 B in FP64), and what the kernel
+    moves when no cell boundary is crossed, without the cells (52 B, 104 B)."""
+    from paper_0909_5603_amd import workloads
+
+    u, Ex, B, cell, off = workloads.pusher_set(n, "crossed", seed=2)
+    s = torch.cuda.current_stream()
+    out = {"particles": n, "steps": nsteps,
+           "fields": "crossed, E = -v x B, gamma log-uniform in [1e2, 1e6]"}
+    for name, prec, dtype, abytes, kbytes in (("fp32", pic.PIC_FP32_SPLIT, torch.float32, 76, 52),
+                                            ("fp64", pic.PIC_FP64, torch.float64, 128, 104)):
+        tu = torch.from_numpy(np.ascontiguousarray(u.T)).to("cuda", dtype).reshape(-1)
+        tE = torch.from_numpy(Ex).to("cuda", dtype)
+        tc = torch.from_numpy(np.ascontiguousarray(cell.T)).to("cuda").reshape(-1)
+        to = torch.from_numpy(np.ascontiguousarray(off.T)).to("cuda", dtype).reshape(-1)
+        ptrs = (tE.data_ptr(), tu.data_ptr(), tc.data_ptr(), to.data_ptr(), s.cuda_stream)
+        for pname, pusher in (("vay", pic.PIC_VAY), ("boris", pic.PIC_BORIS)):
+            pic.pic_push_bench(prec, pusher, n, 3, workloads.PUSH_DT, B, *ptrs)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(s)
+            pic.pic_push_bench(prec, pusher, n, nsteps, workloads.PUSH_DT, B, *ptrs)
+            e1.record(s)
+            e1.synchronize()
+            ms = e0.elapsed_time(e1) / nsteps
+            rate = n / (ms * 1e-3)
+            out[f"{name}_{pname}"] = {"pushes_per_s": rate, "ms_per_launch": ms,
+                                      "GBs_algorithmic": rate * abytes / 1e9,
+                                      "frac": rate * abytes / 1e9 / HBM_PEAK_GBS,
+                                      "GBs_moved_without_crossings": rate * kbytes / 1e9}
+        del tu, tE, tc, to
+        torch.cuda.empty_cache()
+    return out
+
+
 def serving(pic, torch, n_requests, budget_gib, chunk):
     from paper_0909_5603_amd import serve, workloads
 
@@ -279,6 +321,8 @@ def main():
     ap.add_argument("--workload", default="c5", choices=["c5", "c3"])
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-pusher", action="store_true",
+                    help="skip the 2^27-particle pusher microbenchmark")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-filter", action="store_true",
                     help="skip the run with the low-pass current filter")
@@ -357,6 +401,12 @@ def main():
         line["lab_io"] = lc
         log(f"[lab io] antenna + {lc['n_stations']} stations: {lc['lab_io_ms_per_step']:.3f} ms/step "
             f"(step {lc['ms_per_step_events']:.3f} ms)")
+    if not args.no_pusher:
+        pc = pusher_cost(pic, torch)
+        line["pusher"] = pc
+        log("[pusher] 2^27 particles, crossed fields: " + ", ".join(
+            f"{k} {v['pushes_per_s']:.3e}/s ({100 * v['frac']:.0f}%)" for k, v in pc.items()
+            if isinstance(v, dict)))
     if not args.no_serving:
         res = serving(pic, torch, args.serve_requests, budget_gib=96.0, chunk=25)
         line["serving"] = res
