@@ -751,8 +751,11 @@ static void inject(ora_state* s, int64_t n) {
 /* solvers and low-pass digital filtering; the paper gives no filter, the   */
 /* one here is the standard binomial one).  A pass along one axis replaces  */
 /* every value by wm a[q] + ws (a[q-1] + a[q+1]) on the component's own     */
-/* staggered grid: periodic axes wrap, along an open z axis the values      */
-/* outside the component's range count as zero.  N passes of (1/4,1/2,1/4)  */
+/* staggered grid: periodic axes wrap; along an open z axis a value beyond  */
+/* the component's range repeats the value at that end of the range, so a  */
+/* current that streams uniformly out through an end (the drifting plasma)  */
+/* passes unchanged (with zeros beyond the ends, the cut of the end values  */
+/* would act as a steady charge source there).  N passes of (1/4,1/2,1/4)   */
 /* along each axis have the transfer function cos^2N(theta/2) per axis      */
 /* (theta = k * cell); the optional compensating pass (-N/4, 1+N/2, -N/4)   */
 /* multiplies it by 1 + N sin^2(theta/2), which restores the long-wave      */
@@ -774,8 +777,8 @@ static void filter_pass(const ora_state* s, double* a, int zcount, int axis, dou
             lo = a[gidx(s, km, i, j)];
             hi = a[gidx(s, kp, i, j)];
           } else {
-            lo = km >= 0 ? a[gidx(s, km, i, j)] : 0.0;
-            hi = kp < zcount ? a[gidx(s, kp, i, j)] : 0.0;
+            lo = a[gidx(s, km >= 0 ? km : k, i, j)];
+            hi = a[gidx(s, kp < zcount ? kp : k, i, j)];
           }
         } else if (axis == 1) {
           lo = a[gidx(s, k, wrapi(i - 1, nx), j)];

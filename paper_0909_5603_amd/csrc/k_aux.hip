@@ -282,8 +282,8 @@ __global__ void k_jlast(const RunDev* __restrict__ rdp) {
 
 // ------------------------------------------------------------------ filter
 // One stage of the current filter applied to a node scalar (the electron
-// density of the filtered Gauss diagnostic): the same passes and weights as
-// the current's, with the z range of a node-type component.
+// density of the filtered Gauss diagnostic): the same passes, weights and
+// open-end rule as the current's, with the z range of a node-type component.
 template <int DIM>
 __global__ __launch_bounds__(256) void k_filter_nodes(const RunDev* __restrict__ rdp, const double* src,
                                                       double* dst, int stage) {
@@ -306,8 +306,8 @@ __global__ __launch_bounds__(256) void k_filter_nodes(const RunDev* __restrict__
     double lo, hi;
     if (axis == 0) {
       if (rd.open) {
-        lo = k > 0 ? src[q - 1] : 0.0;
-        hi = k + 1 < zc ? src[q + 1] : 0.0;
+        lo = k > 0 ? src[q - 1] : src[q];  // beyond an end: the end value
+        hi = k + 1 < zc ? src[q + 1] : src[q];
       } else {
         lo = src[gidx(rd, wrapi(k - 1, rd.nz), i, j)];
         hi = src[gidx(rd, wrapi(k + 1, rd.nz), i, j)];

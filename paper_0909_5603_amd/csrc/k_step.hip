@@ -992,8 +992,10 @@ __global__ __launch_bounds__(256) void k_efull(const BatchTable* __restrict__ bt
 // (1/4, 1/2, 1/4) for the first passes x axes stages and (-N/4, 1 + N/2,
 // -N/4) for the compensating ones after them.  Stage 0 reads the deposited
 // fixed-point current times its scale, stage s > 0 reads the output of stage
-// s-1, and stage s writes jf[s & 1].  Open z: neighbours outside a
-// component's range count as zero, and points outside it are written as 0.
+// s-1, and stage s writes jf[s & 1].  Open z: a neighbour beyond a
+// component's range repeats the value at that end of the range (a current
+// streaming uniformly out through an end passes unchanged), and points
+// outside the range are written as 0.
 // Runs of a batch with fewer stages skip the later ones.
 template <int DIM, typename R>
 __global__ __launch_bounds__(256) void k_filter(const BatchTable* __restrict__ bt, int stage) {
@@ -1034,6 +1036,8 @@ __global__ __launch_bounds__(256) void k_filter(const BatchTable* __restrict__ b
         if (mok) vm = src[c][qm];
         if (pok) vp = src[c][qp];
       }
+      if (!mok) vm = v0;
+      if (!pok) vp = v0;
       dst[c][q] = cok ? wm * v0 + ws * (vm + vp) : R(0);
     }
   }

@@ -83,22 +83,43 @@ def test_nyquist_mode_removed_by_one_pass(ora):
     st.close()
 
 
-def test_open_z_end_drops_what_leaves_the_range(ora):
+def test_open_z_end_repeats_the_end_value(ora):
+    """Along an open z axis a value beyond a component's range repeats the
+    value at that end, so a pass keeps the sum of what sits at an end (a
+    uniform current streaming out through the end passes unchanged)."""
     st, cfg = _empty(ora, 2, bc_z="open", filter_passes=1)
     ny, nx, nz = st.shape
     st.field(ora.JX)[0, 5, 0] = 1.0  # node-type z component at the first node
     st.field(ora.JZ)[0, 5, cfg["nz"] - 1] = 1.0  # half-type: last valid half point
     st.filter_current()
     jx, jz = st.field(ora.JX)[0], st.field(ora.JZ)[0]
-    # z profile (1/2, 1/4) kept, 1/4 dropped below z = 0; x profile (1/4, 1/2, 1/4)
-    np.testing.assert_allclose(jx[:, 0], [0, 0, 0, 0, 0.125, 0.25, 0.125] + [0] * (nx - 7), atol=1e-15)
-    np.testing.assert_allclose(jx[5, :3], [0.25, 0.125, 0.0], atol=1e-15)
-    assert jx.sum() == pytest.approx(0.75)
-    assert jz[5, cfg["nz"] - 1] == pytest.approx(0.25)
+    # z profile (1/2 + 1/4, 1/4): the neighbour below z = 0 is the end value
+    # itself; x profile (1/4, 1/2, 1/4)
+    np.testing.assert_allclose(jx[:, 0], [0, 0, 0, 0, 0.1875, 0.375, 0.1875] + [0] * (nx - 7), atol=1e-15)
+    np.testing.assert_allclose(jx[5, :3], [0.375, 0.125, 0.0], atol=1e-15)
+    assert jx.sum() == pytest.approx(1.0)
+    assert jz[5, cfg["nz"] - 1] == pytest.approx(0.375)
     assert jz[5, cfg["nz"] - 2] == pytest.approx(0.125)
     assert jz[:, cfg["nz"]:].sum() == 0.0  # nothing written beyond the half-point range
-    assert jz.sum() == pytest.approx(0.75)
+    assert jz.sum() == pytest.approx(1.0)
     st.close()
+
+
+def test_uniform_current_passes_an_open_end_unchanged(ora):
+    """The drifting plasma's current is uniform up to both open ends: every
+    pass, the compensating one included, leaves it as it is, so the filtered
+    electron current still cancels the unfiltered ion background there."""
+    for n, comp in ((1, 0), (2, 1), (5, 1)):
+        st, cfg = _empty(ora, 2, bc_z="open", filter_passes=n, filter_compensate=comp)
+        kz = cfg["nz"]  # half points 0..nz-1, nodes 0..nz
+        st.field(ora.JX)[0, :, :kz + 1] = 0.3
+        st.field(ora.JY)[0, :, :kz + 1] = -1.7
+        st.field(ora.JZ)[0, :, :kz] = 4.9
+        st.filter_current()
+        np.testing.assert_allclose(st.field(ora.JX)[0, :, :kz + 1], 0.3, rtol=1e-14)
+        np.testing.assert_allclose(st.field(ora.JY)[0, :, :kz + 1], -1.7, rtol=1e-14)
+        np.testing.assert_allclose(st.field(ora.JZ)[0, :, :kz], 4.9, rtol=1e-14)
+        st.close()
 
 
 @pytest.mark.parametrize("dims,n,comp", [(2, 2, 1), (3, 1, 0)])
