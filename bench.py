@@ -242,6 +242,33 @@ def lab_io_cost(cfg, pic, torch, fields_ms_plain, nsteps=10, n_stations=32, stri
             "lab_io_ms_per_step": ms["fields"] - fields_ms_plain}
 
 
+def full_run(cfg, pic, torch, passes, compensate):
+    """The workload's whole configured run (cfg["steps"] steps from t = 0), once
+    with the current filter (passes + compensation) and once without: whole-run
+    rate and the state at the end.  Without a filter the short-wavelength
+    instability of the boosted frame grows and heats the plasma, which sends
+    electrons through the out-of-window path; the filter is the paper's cure."""
+    out = {"steps": cfg["steps"]}
+    for name, fp, fc in (("filtered", passes, compensate), ("unfiltered", 0, 0)):
+        run = pic.Run(dict(cfg, filter_passes=fp, filter_compensate=fc), "fp32")
+        d0 = run.diag(pic.PIC_DIAG_PARTICLES)
+        run.synchronize()
+        t0 = time.perf_counter()
+        run.step(cfg["steps"])
+        run.synchronize()
+        sec = time.perf_counter() - t0
+        d1 = run.diag(pic.PIC_DIAG_FIELDS | pic.PIC_DIAG_PARTICLES)
+        run.close()
+        del run
+        torch.cuda.empty_cache()
+        n_box = 0.5 * (d0["n_particles"] + d1["n_particles"])
+        out[name] = {"filter_passes": fp, "filter_compensate": fc,
+                     "value": n_box * cfg["steps"] / sec, "ms_per_step": 1e3 * sec / cfg["steps"],
+                     "U_E": d1["U_E"], "Ez_max": d1["Ez_max"], "KE": d1["KE"],
+                     "slow_path_fraction": d1["n_slow"] / max(1.0, n_box * cfg["steps"])}
+    return out
+
+
 def pusher_cost(pic, torch, nsteps=50, n=1 << 27):
     """Pusher microbenchmark: 2^27 particles, each in its own crossed field
     (E = -v x B, gamma log-uniform in [1e2, 1e6]), one launch per step, the
@@ -321,6 +348,8 @@ def main():
     ap.add_argument("--workload", default="c5", choices=["c5", "c3"])
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-full-run", action="store_true",
+                    help="skip the whole configured run (1000 steps) with and without the filter")
     ap.add_argument("--no-pusher", action="store_true",
                     help="skip the 2^27-particle pusher microbenchmark")
     ap.add_argument("--no-cpu", action="store_true")
@@ -401,6 +430,14 @@ def main():
         line["lab_io"] = lc
         log(f"[lab io] antenna + {lc['n_stations']} stations: {lc['lab_io_ms_per_step']:.3f} ms/step "
             f"(step {lc['ms_per_step_events']:.3f} ms)")
+    if not args.no_full_run:
+        fr = full_run(cfg, pic, torch, passes=4, compensate=1)
+        line["full_run"] = fr
+        for k in ("filtered", "unfiltered"):
+            v = fr[k]
+            log(f"[full run, {k}] {fr['steps']} steps: {v['ms_per_step']:.3f} ms/step, "
+                f"{v['value']:.3e} particle-steps/s, Ez_max {v['Ez_max']:.3g}, "
+                f"slow-path fraction {v['slow_path_fraction']:.2e}")
     if not args.no_pusher:
         pc = pusher_cost(pic, torch)
         line["pusher"] = pc
