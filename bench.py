@@ -199,16 +199,18 @@ def filter_cost(cfg, pic, torch, fields_ms_plain, nsteps=10, passes=1, compensat
     run.step(5)
     run.synchronize()
     ms = pic.pic_step_timed(run.handle, nsteps)
-    stages = (passes + compensate) * (3 if cfg["dims"] == 3 else 2)
+    naxes = 3 if cfg["dims"] == 3 else 2
+    stages = (passes + compensate) * naxes
     npts = run.npts
     run.close()
     del run
     torch.cuda.empty_cache()
     fms = ms["fields"] - fields_ms_plain
-    # algorithmic bytes: stage 0 reads the fixed-point current (3 x 8 B) and
-    # writes the filtered one (3 x 4 B); later stages read and write 3 x 4 B
-    fbytes = npts * (36 + 24 * (stages - 1))
-    return {"passes": passes, "compensate": compensate, "stages": stages,
+    # algorithmic bytes: one launch per axis applies all of that axis's
+    # passes; the z launch reads the fixed-point current (3 x 8 B) and writes
+    # the filtered one (3 x 4 B), the x and y launches read and write 3 x 4 B
+    fbytes = npts * (36 + 24 * (naxes - 1))
+    return {"passes": passes, "compensate": compensate, "stages": stages, "launches": naxes,
             "ms_per_step_events": ms["step"], "fields_ms_per_step": ms["fields"],
             "filter_ms_per_step": fms, "filter_GBs": fbytes / (fms * 1e-3) / 1e9 if fms > 0 else None}
 
@@ -423,7 +425,7 @@ def main():
     if not args.no_filter:
         fc = filter_cost(cfg, pic, torch, ms["fields"])
         line["filter"] = fc
-        log(f"[filter] {fc['stages']} stages: {fc['filter_ms_per_step']:.3f} ms/step "
+        log(f"[filter] {fc['stages']} one-axis passes in {fc['launches']} launches: {fc['filter_ms_per_step']:.3f} ms/step "
             f"(step {fc['ms_per_step_events']:.3f} ms)")
     if not args.no_lab_io:
         lc = lab_io_cost(cfg, pic, torch, ms["fields"])

@@ -968,7 +968,7 @@ __global__ __launch_bounds__(256) void k_efull(const BatchTable* __restrict__ bt
     }
     R jx, jy, jz;
     if (rd.filter_stages > 0) {  // filtered current, already in physical units
-      const Arr3<R> F = PIC_ARR3(R, rd.jf[(rd.filter_stages - 1) & 1]);
+      const Arr3<R> F = PIC_ARR3(R, rd.jf[(DIM == 3 ? 2 : 1) & 1]);
       jx = F[0][q];
       jy = F[1][q];
       jz = F[2][q];
@@ -986,60 +986,171 @@ __global__ __launch_bounds__(256) void k_efull(const BatchTable* __restrict__ bt
   }
 }
 
-// One stage of the low-pass current filter (between the deposit and the E
-// update).  Stage s is a three-point pass along axis s mod (number of axes)
-// on every current component's own staggered grid, with weights
-// (1/4, 1/2, 1/4) for the first passes x axes stages and (-N/4, 1 + N/2,
-// -N/4) for the compensating ones after them.  Stage 0 reads the deposited
-// fixed-point current times its scale, stage s > 0 reads the output of stage
-// s-1, and stage s writes jf[s & 1].  Open z: a neighbour beyond a
-// component's range repeats the value at that end of the range (a current
-// streaming uniformly out through an end passes unchanged), and points
-// outside the range are written as 0.
-// Runs of a batch with fewer stages skip the later ones.
+// Low-pass current filter (between the deposit and the E update), all the
+// passes along one axis per launch.  The binomial passes (1/4, 1/2, 1/4) and
+// the optional compensating pass (-N/4, 1 + N/2, -N/4) along different axes
+// commute, so the filter runs as z, then x, then y.
+//   k_filter_z: one workgroup per transverse column of a filtering run; the
+//     column's three components (the fixed-point deposit times its scale) are
+//     staged in LDS and the passes applied in order on each component's own
+//     z range: periodic z wraps, along an open z axis a neighbour beyond the
+//     range repeats the value at that end (a current streaming uniformly out
+//     through an end passes unchanged); points outside the range are 0.
+//     Writes jf[0].
+//   k_filter_xy: along the periodic x (axis 1, jf[0] -> jf[1]) and y (axis 2,
+//     jf[1] -> jf[0]) axes the passes compose exactly into one (2H+1)-point
+//     stencil, H = N + (compensation), whose weights each workgroup derives
+//     from the binomial coefficients.
+// The E update reads the last axis's output.
+constexpr int FILTER_ZMAX = 2048;  // z points of a column (the cell packing keeps nzf below)
+constexpr int FILTER_HMAX = 17;    // N <= 16 passes plus compensation
+
 template <int DIM, typename R>
-__global__ __launch_bounds__(256) void k_filter(const BatchTable* __restrict__ bt, int stage) {
-  constexpr int NAX = DIM == 3 ? 3 : 2;
+__global__ __launch_bounds__(256) void k_filter_z(const BatchTable* __restrict__ bt) {
+  constexpr int PER = FILTER_ZMAX / 256;
+  __shared__ long long pre[MAX_BATCH + 1];
+  __shared__ R col[3][FILTER_ZMAX];
+  const int n = bt->n;
+  for (int r = threadIdx.x; r < n; r += blockDim.x) {
+    RunC& rd = *bt->run[r];
+    pre[r + 1] = rd.filter_stages > 0 ? rd.nperp : 0;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    long long acc = 0;
+    pre[0] = 0;
+    for (int r = 0; r < n; ++r) {
+      acc += pre[r + 1];
+      pre[r + 1] = acc;
+    }
+  }
+  __syncthreads();
+  const long long items = pre[n];
+  for (long long w = blockIdx.x; w < items; w += gridDim.x) {
+    const int r = __builtin_amdgcn_readfirstlane(locate(pre, n, w));
+    RunC& rd = *bt->run[r];
+    const int nzf = rd.nzf, nz = rd.nz;
+    if (nzf > FILTER_ZMAX) {  // excluded by the cell packing; never staged
+      if (threadIdx.x == 0) g_or(&rd.ctr->err, (unsigned)PIC_ERR_TILE);
+      continue;
+    }
+    const bool open = rd.open != 0;
+    const long long base = (w - pre[r]) * nzf;
+    const Arr3<long long> J = PIC_ARR3(long long, rd.J[rd.ctr->fbuf]);
+    const double jinv = rd.jinv;
+    // z range: nodes (Jx, Jy) 0..nzf-1, half points (Jz) 0..nz-1
+    for (int k = threadIdx.x; k < nzf; k += 256) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+        col[c][k] = k < (c == 2 ? nz : nzf) ? R((double)J[c][base + k] * jinv) : R(0);
+    }
+    __syncthreads();
+    // filter_stages = (passes + compensation) x axes
+    const int np = rd.filter_passes, npass = rd.filter_stages / (DIM == 3 ? 3 : 2);
+    for (int p = 0; p < npass; ++p) {
+      const bool cpass = p >= np;
+      const R ws = cpass ? R(-0.25) * R(np) : R(0.25);
+      const R wm = cpass ? R(1) + R(0.5) * R(np) : R(0.5);
+      R v[3][PER];
+#pragma unroll
+      for (int u = 0; u < PER; ++u) {
+        const int k = threadIdx.x + u * 256;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const int zc = c == 2 ? nz : nzf;
+          R out = R(0);
+          if (k < zc) {
+            const R a = col[c][k];
+            R lo, hi;
+            if (open) {
+              lo = k > 0 ? col[c][k - 1] : a;
+              hi = k + 1 < zc ? col[c][k + 1] : a;
+            } else {
+              lo = col[c][k > 0 ? k - 1 : nz - 1];
+              hi = col[c][k + 1 < nz ? k + 1 : 0];
+            }
+            out = wm * a + ws * (lo + hi);
+          }
+          v[c][u] = out;
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < PER; ++u) {
+        const int k = threadIdx.x + u * 256;
+        if (k < nzf) {
+#pragma unroll
+          for (int c = 0; c < 3; ++c) col[c][k] = v[c][u];
+        }
+      }
+      __syncthreads();
+    }
+    const Arr3<R> dst = PIC_ARR3(R, rd.jf[0]);
+    for (int k = threadIdx.x; k < nzf; k += 256) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) dst[c][base + k] = col[c][k];
+    }
+    __syncthreads();  // the next column reuses col
+  }
+}
+
+template <int DIM, typename R>
+__global__ __launch_bounds__(256) void k_filter_xy(const BatchTable* __restrict__ bt, int axis) {
+  __shared__ R wt[2 * FILTER_HMAX + 1];
+  __shared__ int wrun;
+  if (threadIdx.x == 0) wrun = -1;
+  __syncthreads();
   const XcdSplit xs(bt->cellblk);
   for (long long w = xs.beg; w < xs.end; w += xs.stride) {
     const int r = __builtin_amdgcn_readfirstlane(locate(bt->pre_cellblk, bt->n, w));
     RunC& rd = *bt->run[r];
-    if (stage >= rd.filter_stages) continue;
-    FieldPt<DIM> P;
-    if (!P.init(rd, w - bt->pre_cellblk[r])) continue;
-    const int axis = stage % NAX;
-    const bool cpass = stage >= rd.filter_passes * NAX;
-    const R N = R(rd.filter_passes);
-    const R ws = cpass ? R(-0.25) * N : R(0.25);
-    const R wm = cpass ? R(1) + R(0.5) * N : R(0.5);
-    const unsigned q = P.q;
-    const unsigned qm = axis == 0 ? P.qzm : (axis == 1 ? P.qxm : P.qym);
-    const unsigned qp = axis == 0 ? P.qzp : (axis == 1 ? P.qxp : P.qyp);
-    const Arr3<long long> J = PIC_ARR3(long long, rd.J[rd.ctr->fbuf]);
-    const Arr3<R> src = PIC_ARR3(R, rd.jf[(stage + 1) & 1]);
-    const Arr3<R> dst = PIC_ARR3(R, rd.jf[stage & 1]);
-    const double jinv = rd.jinv;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      // z stagger of J like E: Jx, Jy on nodes, Jz on half points
-      const bool half = c == 2;
-      const bool cok = half ? P.c_h : true;
-      const bool mok = axis != 0 || P.zm_ok;
-      const bool pok = axis != 0 || (half ? P.zp_h : P.zp_n);
-      R v0 = R(0), vm = R(0), vp = R(0);
-      if (stage == 0) {
-        if (cok) v0 = R((double)J[c][q] * jinv);
-        if (mok) vm = R((double)J[c][qm] * jinv);
-        if (pok) vp = R((double)J[c][qp] * jinv);
-      } else {
-        if (cok) v0 = src[c][q];
-        if (mok) vm = src[c][qm];
-        if (pok) vp = src[c][qp];
+    if (rd.filter_stages == 0) continue;
+    const int np = rd.filter_passes;
+    const int H = rd.filter_stages / (DIM == 3 ? 3 : 2);  // passes + compensation
+    const bool comp = H > np;
+    if (r != wrun) {  // uniform over the workgroup: the weights of this run
+      __syncthreads();
+      const int m = (int)threadIdx.x - H;
+      if (m >= -H && m <= H) {
+        // binomial weight C(2N, N+m) / 4^N of offset m (0 beyond +-N)
+        auto bin = [np](int o) -> double {
+          if (o < -np || o > np) return 0.0;
+          const int kk = np + o;
+          double c = 1.0;
+          for (int t = 1; t <= kk; ++t) c = c * (double)(2 * np - kk + t) / (double)t;
+          return ldexp(c, -2 * np);
+        };
+        double wv = bin(m);
+        if (comp) wv = (1.0 + 0.5 * np) * bin(m) - 0.25 * np * (bin(m - 1) + bin(m + 1));
+        wt[m + H] = R(wv);
       }
-      if (!mok) vm = v0;
-      if (!pok) vp = v0;
-      dst[c][q] = cok ? wm * v0 + ws * (vm + vp) : R(0);
+      if (threadIdx.x == 0) wrun = r;
+      __syncthreads();
     }
+    const long long q = (w - bt->pre_cellblk[r]) * CELL_BLOCK + threadIdx.x;
+    if (q >= rd.npts) continue;
+    const int nzf = rd.nzf, nx = rd.nx, ny = rd.ny;
+    const int k = (int)(q % nzf);
+    const long long t = q / nzf;
+    const int i = (int)(t % nx), j = (int)(t / nx);
+    const int na = axis == 1 ? nx : ny;
+    const int ia = axis == 1 ? i : j;
+    const long long stride = axis == 1 ? (long long)nzf : (long long)nx * nzf;
+    const Arr3<R> src = PIC_ARR3(R, rd.jf[(axis - 1) & 1]);
+    const Arr3<R> dst = PIC_ARR3(R, rd.jf[axis & 1]);
+    const bool half_ok = !rd.open || k < rd.nz;  // Jz has no point at k = nz
+    R acc[3] = {R(0), R(0), R(0)};
+    for (int m = -H; m <= H; ++m) {
+      const int ib = ((ia + m) % na + na) % na;  // periodic; H may exceed na
+      const long long qq = q + (long long)(ib - ia) * stride;
+      const R wm = wt[m + H];
+      acc[0] += wm * src[0][qq];
+      acc[1] += wm * src[1][qq];
+      if (half_ok) acc[2] += wm * src[2][qq];
+    }
+    dst[0][q] = acc[0];
+    dst[1][q] = acc[1];
+    dst[2][q] = acc[2];
   }
 }
 
@@ -1128,8 +1239,11 @@ void launch_particles(int dims, int prec, int pusher, const BatchTable* bt, int 
 template <int DIM, typename R>
 static void lf(const BatchTable* bt, int grid, int filter_stages, long long ant_plane, hipStream_t s) {
   constexpr int prec = sizeof(R) == 8 ? 1 : 0;
-  for (int st = 0; st < filter_stages; ++st)
-    hipLaunchKernelGGL((k_filter<DIM, R>), dim3(grid), dim3(256), 0, s, bt, st);
+  if (filter_stages > 0) {
+    hipLaunchKernelGGL((k_filter_z<DIM, R>), dim3(grid), dim3(256), 0, s, bt);
+    hipLaunchKernelGGL((k_filter_xy<DIM, R>), dim3(grid), dim3(256), 0, s, bt, 1);
+    if (DIM == 3) hipLaunchKernelGGL((k_filter_xy<DIM, R>), dim3(grid), dim3(256), 0, s, bt, 2);
+  }
   hipLaunchKernelGGL((k_bhalf<DIM, R>), dim3(grid), dim3(256), 0, s, bt);
   if (ant_plane > 0) launch_antenna(prec, bt, ant_plane, 0, grid, s);
   hipLaunchKernelGGL((k_efull<DIM, R>), dim3(grid), dim3(256), 0, s, bt);
