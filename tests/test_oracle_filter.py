@@ -155,3 +155,20 @@ def test_filtered_gauss_law_open_ends(ora):
     assert cont < 1e-12
     assert d["gauss_drift"] < 1e-12
     st.close()
+
+
+def test_open_ends_stay_quiet_over_a_long_filtered_run(ora):
+    """Parity configuration, 2 passes + compensation, 450 steps: |E_z| at the
+    cells next to both open ends stays at the interior's level.  (With zeros
+    beyond the ends instead of the end values, the filtered electron current
+    fell short of the ion background there and E_z grew linearly: about 160
+    times the interior median after 450 steps.)"""
+    cfg = workloads.config("c1", filter_passes=2, filter_compensate=1)
+    st = ora.State(cfg)
+    st.step(450)
+    prof = np.abs(st.field(ora.EZ)[0]).max(axis=0)[: cfg["nz"]]  # max over x, half points 0..nz-1
+    st.close()
+    ends = np.concatenate([prof[:3], prof[-3:]])
+    med = np.median(prof)
+    print(f"\nend cells {ends.round(4)}, interior median {med:.4f}")
+    assert ends.max() < 5.0 * med
