@@ -1054,6 +1054,7 @@ __global__ __launch_bounds__(256) void k_filter_z(const BatchTable* __restrict__
       R v[3][PER];
 #pragma unroll
       for (int u = 0; u < PER; ++u) {
+        if (u * 256 >= nzf) break;  // uniform: the column's last slot was done
         const int k = threadIdx.x + u * 256;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
@@ -1077,6 +1078,7 @@ __global__ __launch_bounds__(256) void k_filter_z(const BatchTable* __restrict__
       __syncthreads();
 #pragma unroll
       for (int u = 0; u < PER; ++u) {
+        if (u * 256 >= nzf) break;
         const int k = threadIdx.x + u * 256;
         if (k < nzf) {
 #pragma unroll
@@ -1140,13 +1142,21 @@ __global__ __launch_bounds__(256) void k_filter_xy(const BatchTable* __restrict_
     const Arr3<R> dst = PIC_ARR3(R, rd.jf[axis & 1]);
     const bool half_ok = !rd.open || k < rd.nz;  // Jz has no point at k = nz
     R acc[3] = {R(0), R(0), R(0)};
+    // periodic index of the first tap (H may exceed na), then step by one
+    int ib = ((ia - H) % na + na) % na;
+    long long qq = q + (long long)(ib - ia) * stride;
+    const long long wrap = (long long)na * stride;
     for (int m = -H; m <= H; ++m) {
-      const int ib = ((ia + m) % na + na) % na;  // periodic; H may exceed na
-      const long long qq = q + (long long)(ib - ia) * stride;
       const R wm = wt[m + H];
       acc[0] += wm * src[0][qq];
       acc[1] += wm * src[1][qq];
       if (half_ok) acc[2] += wm * src[2][qq];
+      ++ib;
+      qq += stride;
+      if (ib == na) {
+        ib = 0;
+        qq -= wrap;
+      }
     }
     dst[0][q] = acc[0];
     dst[1][q] = acc[1];
