@@ -136,15 +136,16 @@ __device__ __forceinline__ int sort_item_run(const SortItems& si, int n, long lo
 // tile: rows of tiles of tx x ty cells, the tiles of a row left to right,
 // the cells of a tile row by row; the last row and column of tiles may be
 // narrower.
-__device__ __forceinline__ void blocked_cell(long long b, int nx, int ny, int tx, int ty, int& i, int& j) {
-  const int tyi = (int)(b / ((long long)ty * nx));
-  long long r = b - (long long)tyi * ty * nx;
-  const int wy = min(ty, ny - tyi * ty);
-  const int txi = (int)(r / ((long long)tx * wy));
-  r -= (long long)txi * tx * wy;
-  const int wx = min(tx, nx - txi * tx);
-  j = tyi * ty + (int)(r / wx);
-  i = txi * tx + (int)(r % wx);
+__device__ __forceinline__ void blocked_cell(unsigned b, int nx, int ny, int tx, int ty, int& i, int& j) {
+  const unsigned tyi = b / (unsigned)(ty * nx);
+  unsigned r = b - tyi * (unsigned)(ty * nx);
+  const int wy = min(ty, ny - (int)tyi * ty);
+  const unsigned txi = r / (unsigned)(tx * wy);
+  r -= txi * (unsigned)(tx * wy);
+  const int wx = min(tx, nx - (int)txi * tx);
+  const unsigned jr = r / (unsigned)wx;
+  j = (int)tyi * ty + (int)jr;
+  i = (int)txi * tx + (int)(r - jr * (unsigned)wx);
 }
 
 template <typename R>
@@ -180,11 +181,16 @@ __global__ __launch_bounds__(256) void k_inject(const BatchTable* __restrict__ b
       // addresses (an FP64 tile plane has 8x4 cells, so there a wavefront
       // holds two slots of it).  The lattice id does not depend on this
       // order.
-      const long long K = c.next_col + q / per_col;
-      const long long rem = q % per_col;
-      const long long sl = rem / rd.nperp;
+      // q < nnew and per_col are below the capacity (< 2^31): 32-bit
+      // unsigned divisions, a few instructions each instead of the long
+      // 64-bit sequences
+      const unsigned qu = (unsigned)q, pc = (unsigned)per_col, npu = (unsigned)rd.nperp;
+      const unsigned kq = qu / pc, rem = qu - kq * pc;
+      const unsigned slu = rem / npu;
+      const long long K = c.next_col + (long long)kq;
+      const long long sl = (long long)slu;
       int i, j;
-      blocked_cell(rem % rd.nperp, rd.nx, rd.dims == 3 ? rd.ny : 1, rd.dims == 3 ? Tile<3, R>::TX : Tile<2, R>::TX,
+      blocked_cell(rem - slu * npu, rd.nx, rd.dims == 3 ? rd.ny : 1, rd.dims == 3 ? Tile<3, R>::TX : Tile<2, R>::TX,
                    rd.dims == 3 ? Tile<3, R>::TY : 1, i, j);
       const long long cperp = (long long)j * rd.nx + i;
       const uint64_t L = (uint64_t)((K * rd.nperp + cperp) * rd.ppc + sl);
