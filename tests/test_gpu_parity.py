@@ -65,6 +65,11 @@ CASES = {
     "c1_periodic": lambda: workloads.config("c1", nz=64, bc_z="periodic"),
     "3d_open": lambda: _small3d(),
     "3d_periodic": lambda: _small3d(nz=32, bc_z="periodic"),
+    # smallest boxes: one 8x8x8 tile (two 8x8x4 tiles in FP64), smaller than
+    # a tile's LDS window, which then wraps onto itself in every direction
+    "3d_min_periodic": lambda: _small3d(nz=8, nx=8, ny=8, bc_z="periodic"),
+    "3d_min_open": lambda: _small3d(nz=8, nx=8, ny=8),
+    "2d_min_periodic": lambda: workloads.config("c1", nz=16, nx=16, bc_z="periodic"),
 }
 
 
@@ -112,7 +117,7 @@ def test_steps_fp64_match_oracle(case):
     st.close()
 
 
-@pytest.mark.parametrize("case", ["c1", "3d_open"])
+@pytest.mark.parametrize("case", ["c1", "3d_open", "3d_min_periodic"])
 def test_fp32_momentum_and_continuity_10_steps(case):
     cfg = CASES[case]()
     run = pic.Run(cfg, "fp32", continuity=True)
