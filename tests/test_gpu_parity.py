@@ -247,3 +247,45 @@ def test_invalid_parameters_rejected():
     with pytest.raises(pic.PicError) as e:
         pic.pic_init_boosted(p, buf.data_ptr(), 1024, torch.cuda.current_stream().cuda_stream)
     assert e.value.status == -2
+
+
+def _largest_nz(cfg):
+    """Largest nz the library accepts for cfg (the z cell index, reservoir
+    included, must fit the packed cell)."""
+    lo, hi = 8, 4096
+    while lo < hi:
+        mid = (lo + hi + 1) // 2
+        try:
+            pic.pic_state_bytes(pic.make_params(dict(cfg, nz=mid)))
+            lo = mid
+        except pic.PicError:
+            hi = mid - 1
+    return lo
+
+
+@pytest.mark.parametrize("case", ["2d_max_nz", "3d_max_nx", "3d_max_ny"])
+def test_largest_accepted_sizes_match_oracle(case):
+    """Boxes at the limits of the packed cell index (z with its reservoir,
+    1024 cells across x or y): FP64 steps match the oracle to rounding."""
+    if case == "2d_max_nz":
+        cfg = workloads.config("c1", nx=16, ppc=1)
+        cfg["nz"] = _largest_nz(cfg)
+        with pytest.raises(pic.PicError):
+            pic.pic_state_bytes(pic.make_params(dict(cfg, nz=cfg["nz"] + 1)))
+    elif case == "3d_max_nx":
+        cfg = _small3d(nz=8, nx=1024, ny=8, ppc=1)
+    else:
+        cfg = _small3d(nz=8, nx=8, ny=1024, ppc=1)
+    run = pic.Run(cfg, "fp64")
+    st = oracle.State(cfg)
+    run.step(5)
+    st.step(5)
+    g, o, m = _match(run.particles(), st.particles())
+    print(f"\n{case}: nz {cfg['nz']} nx {cfg['nx']} ny {cfg.get('ny')}: {m} particles")
+    assert m == st.particles()["id"].size
+    assert _u_relerr(g, o).max() < 1e-10
+    for k in ("z", "x", "y"):
+        assert np.abs(g[k] - o[k]).max() < 1e-10
+    assert _field_relerr(run, st) < 1e-10
+    run.close()
+    st.close()
