@@ -116,17 +116,28 @@ def test_whole_run_with_four_passes_stays_stable_512x256x256():
     short-wavelength instability is kept down.  E_z stays below 2 at every
     check (0.79-0.85 measured; one pass reaches 33 by the end, no filter
     173), no electron leaves its tile window, and the kinetic energy stays
-    constant to 1e-3."""
+    constant to 1e-3.  The split-precision run keeps field energies, wake
+    amplitude and kinetic energy within 1e-3 of the FP64 run at every check
+    (about 1e-5 measured)."""
     cfg = workloads.config("c5", filter_passes=4, filter_compensate=1)
-    run = pic.Run(cfg, "fp32")
-    ke0 = run.diag(pic.PIC_DIAG_PARTICLES)["KE"]
-    for _ in range(cfg["steps"] // 200):
-        run.step(200)
-        d = run.diag(pic.PIC_DIAG_FIELDS | pic.PIC_DIAG_PARTICLES)
-        print(f"\nstep {d['step']}: Ez_max {d['Ez_max']:.3f}, U_E {d['U_E']:.1f}, KE {d['KE']:.6e}, "
-              f"out-of-window {d['n_slow']}", flush=True)
-        assert d["Ez_max"] < 2.0
-        assert d["n_slow"] == 0
-        assert abs(d["KE"] - ke0) < 1e-3 * ke0
-    assert d["step"] == cfg["steps"]
-    run.close()
+    hist = {}
+    for prec in ("fp64", "fp32"):
+        run = pic.Run(cfg, prec)
+        ke0 = run.diag(pic.PIC_DIAG_PARTICLES)["KE"]
+        hist[prec] = []
+        for _ in range(cfg["steps"] // 200):
+            run.step(200)
+            d = run.diag(pic.PIC_DIAG_FIELDS | pic.PIC_DIAG_PARTICLES)
+            print(f"\n{prec} step {d['step']}: Ez_max {d['Ez_max']:.4f}, U_E {d['U_E']:.3f}, "
+                  f"KE {d['KE']:.7e}, out-of-window {d['n_slow']}", flush=True)
+            assert d["Ez_max"] < 2.0
+            assert d["n_slow"] == 0
+            assert abs(d["KE"] - ke0) < 1e-3 * ke0
+            hist[prec].append(d)
+        assert d["step"] == cfg["steps"]
+        run.close()
+        del run
+        torch.cuda.empty_cache()
+    for a, b in zip(hist["fp32"], hist["fp64"]):
+        for k in ("U_E", "U_B", "Ez_max", "KE"):
+            assert a[k] == pytest.approx(b[k], rel=1e-3), (a["step"], k)
