@@ -70,6 +70,11 @@ CASES = {
     "3d_min_periodic": lambda: _small3d(nz=8, nx=8, ny=8, bc_z="periodic"),
     "3d_min_open": lambda: _small3d(nz=8, nx=8, ny=8),
     "2d_min_periodic": lambda: workloads.config("c1", nz=16, nx=16, bc_z="periodic"),
+    # z not a multiple of the tile depth: a ragged last tile, whose window
+    # also wraps across the periodic z boundary
+    "3d_ragged_z_periodic": lambda: _small3d(nz=27, bc_z="periodic"),
+    "3d_ragged_z_open": lambda: _small3d(nz=29),
+    "2d_ragged_z_periodic": lambda: workloads.config("c1", nz=40, nx=32, bc_z="periodic"),
 }
 
 
@@ -117,7 +122,7 @@ def test_steps_fp64_match_oracle(case):
     st.close()
 
 
-@pytest.mark.parametrize("case", ["c1", "3d_open", "3d_min_periodic"])
+@pytest.mark.parametrize("case", ["c1", "3d_open", "3d_min_periodic", "3d_ragged_z_periodic"])
 def test_fp32_momentum_and_continuity_10_steps(case):
     cfg = CASES[case]()
     run = pic.Run(cfg, "fp32", continuity=True)
