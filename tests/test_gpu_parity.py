@@ -82,6 +82,10 @@ CASES = {
     # wavelength is long enough to be resolved without the boost
     "2d_lab_frame": lambda: workloads.config("c1", gamma_boost=1.0, lambda0_um=20.0),
     "3d_lab_frame": lambda: _small3d(nz=24, gamma_boost=1.0, lambda0_um=20.0),
+    # the other polarisation in each dimension: in the simulation plane in
+    # 2D (E along x), along y in 3D
+    "2d_pol_x": lambda: workloads.config("c1", nz=64, pol_axis=1),
+    "3d_pol_y": lambda: _small3d(nz=24, pol_axis=2),
 }
 
 
