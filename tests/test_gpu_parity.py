@@ -237,14 +237,32 @@ def test_no_plasma_and_no_laser_edge_cases():
     st.close()
 
 
-def test_boris_option_matches_oracle_boris():
-    cfg = workloads.config("c1", nz=32, nx=16, pusher="boris")
+@pytest.mark.parametrize("dims", [2, 3])
+def test_boris_option_matches_oracle_boris(dims):
+    """The Boris pusher selected in the step kernels (2D, and the 3D
+    instantiations): FP64 matches the oracle's Boris, split precision keeps
+    the FP32 momentum bound."""
+    if dims == 2:
+        cfg = workloads.config("c1", nz=32, nx=16, pusher="boris")
+    else:
+        cfg = _small3d(nz=24, pusher="boris")
     run = pic.Run(cfg, "fp64")
     st = oracle.State(cfg)
     run.step(5)
     st.step(5)
     g, o, m = _match(run.particles(), st.particles())
+    assert m == st.particles()["id"].size
     assert _u_relerr(g, o).max() < 1e-10
+    assert _field_relerr(run, st) < 1e-10
+    run.close()
+    st.close()
+    run = pic.Run(cfg, "fp32")
+    st = oracle.State(cfg, round_f32=True)
+    run.step(5)
+    st.step(5)
+    g, o, m = _match(run.particles(), st.particles())
+    assert m > 0.99 * st.particles()["id"].size
+    assert _u_relerr(g, o).max() <= 1e-5
     run.close()
     st.close()
 
