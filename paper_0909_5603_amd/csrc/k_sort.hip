@@ -178,19 +178,37 @@ __global__ __launch_bounds__(256) void k_inject(const BatchTable* __restrict__ b
       // the 8x8 cells of one tile's transverse plane, which the sort keeps
       // together, so the lanes of a wavefront of the step kernel start in 64
       // different cells and their LDS current atomics do not share
-      // addresses (an FP64 tile plane has 8x4 cells, so there a wavefront
-      // holds two slots of it).  The lattice id does not depend on this
-      // order.
+      // addresses; smaller planes interleave columns (below).  The lattice
+      // id does not depend on this order.
       // q < nnew and per_col are below the capacity (< 2^31): 32-bit
       // unsigned divisions, a few instructions each instead of the long
       // 64-bit sequences
       const unsigned qu = (unsigned)q, pc = (unsigned)per_col, npu = (unsigned)rd.nperp;
-      const unsigned kq = qu / pc, rem = qu - kq * pc;
-      const unsigned slu = rem / npu;
+      unsigned kq, slu, bq;
+      // cells of one tile plane (8x8 split 3D, 8x4 FP64 3D, 16 in 2D) and
+      // the columns a wavefront interleaves so that it still covers 64 cells
+      const unsigned plane = rd.dims == 3 ? (unsigned)(Tile<3, R>::TX * Tile<3, R>::TY) : (unsigned)Tile<2, R>::TX;
+      const unsigned ncw = 64 / plane;
+      const unsigned ncol = (unsigned)(nnew / per_col);
+      if (ncw > 1 && ncol >= ncw && qu / (ncw * pc) < ncol / ncw) {  // ncw * pc <= nnew < 2^31
+        // columns in groups of ncw: a wavefront creates one slot of one
+        // plane in each of columns K .. K+ncw-1 (different z cells), so the
+        // step kernel's wavefronts still start in 64 different cells
+        const unsigned kg = qu / (ncw * pc), r1 = qu - kg * ncw * pc;
+        slu = r1 / (ncw * npu);
+        const unsigned r2 = r1 - slu * ncw * npu, blk = r2 / 64, within = r2 - blk * 64;
+        kq = ncw * kg + within / plane;
+        bq = blk * plane + within % plane;
+      } else {  // one column at a time (also the columns left over from the groups)
+        kq = qu / pc;
+        const unsigned rem = qu - kq * pc;
+        slu = rem / npu;
+        bq = rem - slu * npu;
+      }
       const long long K = c.next_col + (long long)kq;
       const long long sl = (long long)slu;
       int i, j;
-      blocked_cell(rem - slu * npu, rd.nx, rd.dims == 3 ? rd.ny : 1, rd.dims == 3 ? Tile<3, R>::TX : Tile<2, R>::TX,
+      blocked_cell(bq, rd.nx, rd.dims == 3 ? rd.ny : 1, rd.dims == 3 ? Tile<3, R>::TX : Tile<2, R>::TX,
                    rd.dims == 3 ? Tile<3, R>::TY : 1, i, j);
       const long long cperp = (long long)j * rd.nx + i;
       const uint64_t L = (uint64_t)((K * rd.nperp + cperp) * rd.ppc + sl);

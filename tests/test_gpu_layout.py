@@ -5,8 +5,10 @@ plasma columns are created with the lattice slot outermost and the transverse
 cells enumerated tile by tile, and the sort keeps each wavefront's particles
 in order, so every aligned group of one tile plane's worth of slots (8x8 = 64
 cells in 3D split precision, 8x4 = 32 in FP64, 16 in 2D) holds one lattice
-slot of one column and covers that many different cells: the lanes of a
-step-kernel wavefront do not add their currents to the same LDS addresses.
+slot of one column, and where a plane is smaller than a wavefront the columns
+are interleaved, so every aligned group of 64 slots covers 64 different
+cells: the lanes of a step-kernel wavefront do not add their currents to the
+same LDS addresses.
 """
 import numpy as np
 import pytest
@@ -55,7 +57,20 @@ def test_aligned_groups_are_one_slot_of_one_tile_plane(case):
     for name, v in (("column", col), ("slot", slot)):
         v = v.reshape(g, group)
         assert (v == v[:, :1]).all(), f"a group mixes lattice {name}s"
-    cells = np.sort(cell.reshape(g, group), axis=1)
+    # wavefront-sized groups: one slot, consecutive columns, 64 distinct cells
+    w = n // 64
+    assert n % 64 == 0
+    ws, wc = slot.reshape(w, 64), col.reshape(w, 64)
+    ncw = 64 // group
+    # the columns left over when their count is not a multiple of ncw keep
+    # one column per wavefront; they are the topmost ones
+    ncol = int(col.max()) + 1
+    full = wc.max(axis=1) < ncol - ncol % ncw
+    assert full.mean() > 0.9
+    assert (ws == ws[:, :1])[full].all()
+    assert ((wc.max(axis=1) - wc.min(axis=1))[full] <= ncw - 1).all()
+    cells = np.sort(cell.reshape(w, 64), axis=1)
     dup = (cells[:, 1:] == cells[:, :-1]).any(axis=1)
-    print(f"\n{case}: {n} particles, {g} groups of {group}, groups with a repeated cell: {dup.sum()}")
-    assert not dup.any()
+    print(f"\n{case}: {n} particles, {w} wavefront groups ({full.sum()} from interleaved columns), "
+          f"with a repeated cell: {dup[full].sum()}")
+    assert not dup[full].any()
