@@ -89,14 +89,17 @@ typedef struct {
    * the binomial stencil (1/4, 1/2, 1/4) along every axis on each
    * component's own staggered grid, then, if filter_compensate = 1, one pass
    * of (-N/4, 1 + N/2, -N/4) per axis.  Periodic axes wrap; along an open z
-   * axis values outside a component's range count as zero.  The continuity
+   * axis a neighbour beyond a component's range repeats the value at that
+   * end (a current streaming uniformly out through the end passes
+   * unchanged); points outside the range stay zero.  The continuity
    * diagnostic uses the deposited current, the Gauss diagnostic the filtered
    * electron density.  0 = no filter. */
   int filter_passes;
   int filter_compensate;
-  /* Laboratory-frame stations (Sec. 2: a boosted-frame run is diagnosed at
-   * stations fixed in the laboratory, sampled at a succession of lab times,
-   * with interpolation because lab events do not fall on the boosted grid).
+  /* Laboratory-frame stations (Sec. 2, third paragraph: results are wanted
+   * in the laboratory, so lab-fixed planes record the boosted-frame fields
+   * at the lab times their events map to, interpolated because those events
+   * are not on the boosted grid).
    * Station q (0 <= q < n_stations) is the plane z_lab = Z_q = station_z0 +
    * q station_dz (c/omega_p, lab frame).  At boosted time t' = n dt it sits
    * at z' = Z_q / gamma_b - beta_b t' and the event it samples has lab time
@@ -116,8 +119,9 @@ typedef struct {
   double station_z0, station_dz;
   int station_stride;
   int station_cap;
-  /* Laser source (Sec. 2: the laser is injected at a plane fixed in the
-   * laboratory frame and drifting in the boosted frame).  laser_antenna = 0:
+  /* Laser source (Sec. 2, second paragraph: the pulse may enter through a
+   * plane at rest in the laboratory, which moves at -beta_b in the boosted
+   * frame).  laser_antenna = 0:
    * the pulse is placed in the box at t' = 0, centred at nz dz / 2.
    * laser_antenna = 1: the lab plane z = antenna_z_lab (c/omega_p) emits it;
    * the envelope peak crosses the plane at lab time antenna_t_peak.  In the
@@ -159,21 +163,34 @@ typedef struct {
 
 enum { PIC_DIAG_FIELDS = 1u, PIC_DIAG_PARTICLES = 2u, PIC_DIAG_GAUSS = 4u, PIC_DIAG_ALL = 7u };
 
-/* Bytes of device memory a run of these parameters needs.  Pure host
- * function; used for admission by memory budget.  Returns PIC_EINVAL for
- * invalid parameters. */
+/* Bytes of device memory a run of these parameters needs (Sec. 2, second
+ * paragraph: the run's size is that of the boosted-frame problem, a box of
+ * nz x nx x ny cells holding the plasma at gamma_b times the laboratory
+ * density as ppc electrons per cell, plus the reservoir and tile slack).
+ * Pure host function, no device call; used for admission by memory budget.
+ * Returns PIC_EINVAL for invalid parameters. */
 pic_status pic_state_bytes(const pic_lab_params* p, size_t* bytes);
 
 /* Transform the laboratory inputs to the boosted frame and lay out the run in
  * dev_buf (Sec. 2, second paragraph: Doppler-shifted laser, denser drifting
- * plasma).  Enqueues the laser transform, plasma creation and the first tile
- * sort on `hip_stream` (a hipStream_t; NULL means the null stream) and
- * returns at once.  dev_buf: device pointer to >= pic_state_bytes() bytes,
- * owned by the caller. */
+ * plasma).  Enqueues on `hip_stream` (a hipStream_t; NULL means the null
+ * stream) the copies of the run's descriptors, the laser transform, the
+ * plasma creation, the first tile sort and the Gauss-law reference, and
+ * returns without waiting for the kernels.  The descriptor copies come from
+ * pageable host memory kept in the handle, which HIP performs synchronously:
+ * they wait for work enqueued earlier on the same stream (give a new run an
+ * idle stream to start it without waiting).  dev_buf: device pointer to
+ * >= pic_state_bytes() bytes, 256-byte aligned, owned by the caller and
+ * untouched by anything else until pic_free.  Errors: PIC_EINVAL, PIC_ECFL,
+ * PIC_EBUDGET (buffer too small) and PIC_EHIP are returned before anything
+ * is left enqueued; device-side errors of the kernels show in err_bits of
+ * the next pic_diag. */
 pic_status pic_init_boosted(const pic_lab_params* p, void* dev_buf, size_t bytes,
                             void* hip_stream, pic_run** out);
 
-/* Enqueue nsteps full PIC steps (gather, modified-Lorentz push, move,
+/* Enqueue nsteps full PIC steps (Sec. 2, third paragraph: the system is
+ * evolved in the boosted frame; Sec. 2, first paragraph: the pusher with the
+ * modified Lorentz force): gather, modified-Lorentz push, move,
  * charge-conserving deposit, Yee update; tile sort and plasma injection
  * every sort_every steps, and a tile sort alone within four steps after a
  * step in which more than 1/128 of the particles left their tiles' LDS
@@ -182,9 +199,13 @@ pic_status pic_init_boosted(const pic_lab_params* p, void* dev_buf, size_t bytes
  * it.  Asynchronous. */
 pic_status pic_step(pic_run* run, int nsteps);
 
-/* Advance several runs together: their tiles share the same kernel launches.
- * All runs must have the same dims and precision and share one stream (the
- * first run's).  nsteps[i] may differ; runs drop out when done. */
+/* Advance several runs together (the serving pattern: each run is the Sec. 2,
+ * third paragraph, boosted-frame evolution of pic_step): their tiles share
+ * the same kernel launches, enqueued on the first run's stream.  All runs
+ * must have the same dims, precision and pusher, no continuity
+ * diagnostics, and no work pending on another stream (order it before the
+ * call, e.g. with an event).  nsteps[i] >= 0 may differ; runs drop out when
+ * done.  Asynchronous; PIC_EINVAL for an invalid batch, nothing enqueued. */
 pic_status pic_step_batch(pic_run* const* runs, const int* nsteps, int n);
 
 /* Enqueue nsteps steps without graph replay, bracketing each stage with HIP
@@ -195,8 +216,12 @@ pic_status pic_step_batch(pic_run* const* runs, const int* nsteps, int n);
  * For measurement; the state advances exactly as with pic_step. */
 pic_status pic_step_timed(pic_run* run, int nsteps, double ms[4]);
 
-/* Compute diagnostics (what = PIC_DIAG_* mask); synchronises the run's
- * stream.  Returns PIC_ESTATE if the device error word is set. */
+/* Compute diagnostics (what = PIC_DIAG_* mask) of the boosted-frame state
+ * (Sec. 2, third paragraph: the outputs of the run; Sec. 3.1 compares runs
+ * by field and particle energies): field energies, wake amplitude, kinetic
+ * energy, particle count, continuity residual and Gauss-law drift, defined
+ * on pic_diag_out above.  Synchronises the run's stream.  Returns
+ * PIC_ESTATE if the device error word is set (out is still filled). */
 pic_status pic_diag(pic_run* run, unsigned what, pic_diag_out* out);
 
 /* Number of particle slots in storage order (live and dead) and of live ones. */

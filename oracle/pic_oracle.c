@@ -380,10 +380,10 @@ static int zlimit(const ora_state* s, int comp) { return zvalid_count(s, comp); 
 
 /* B -= dt/2 curl E  (one half step) */
 /* ------------------------------------------------------------------------ */
-/* Laser antenna (Sec. 2: the laser is injected at a plane fixed in the     */
-/* laboratory frame, which drifts in the boosted frame).  The lab plane     */
-/* z = Z_a sits at z'_a(t') = Z_a / gamma_b - beta_b t' and moves at        */
-/* -beta_b.  Wanted: the boosted incident wave (E_i, B_i) above the plane   */
+/* Laser antenna (Sec. 2, second paragraph): the pulse enters through a    */
+/* plane at rest in the laboratory, moving at -beta_b in the boosted frame. */
+/* The lab plane z = Z_a sits at z'_a(t') = Z_a / gamma_b - beta_b t'.     */
+/* Wanted: the boosted incident wave (E_i, B_i) above the plane   */
 /* and nothing below, i.e. the field H (E_i, B_i) with H(z', t') = 1 where  */
 /* z' > z'_a(t'), else 0.  In the continuum the step's derivatives leave    */
 /* surface sources on the plane (an electric current J and a magnetic       */

@@ -1,5 +1,6 @@
-// Laser antenna on the device (Sec. 2: the laser is injected at a plane fixed
-// in the laboratory frame, drifting in the boosted frame).
+// Laser antenna on the device (Sec. 2, second paragraph): the pulse enters
+// the box through a plane that is at rest in the laboratory and therefore
+// moves at -beta_b in the boosted frame.
 //
 // The lab plane z = Z_a sits at z'_a(t') = Z_a / gamma_b - beta_b t'.  The
 // grid is made to carry H (E_i, B_i), the boosted incident wave above the

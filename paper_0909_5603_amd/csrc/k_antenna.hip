@@ -1,5 +1,6 @@
-// Laser antenna sources in the field update (Sec. 2: the laser is injected at
-// a plane fixed in the laboratory, drifting in the boosted frame).
+// Laser antenna sources in the field update (Sec. 2, second paragraph): the
+// pulse enters through a laboratory-fixed plane, which moves at -beta_b in
+// the boosted frame.
 //
 // Two launches per step, for the runs of the table whose antenna is on:
 //   phase 0, after the B pass:  B^{n+1/2} -= dt M^n;

@@ -379,8 +379,130 @@ __device__ __forceinline__ int new_cell(RunC& rd, int k, int i, int j, const int
   return cell_pack(k1, i1, j1) | (dead ? (int)DEAD : 0);
 }
 
-// Occupancy of the 3D particle kernel.  Its LDS window (111 KiB in split
-// precision, 115 KiB in FP64) admits one workgroup per CU, so the workgroup
+// Per-tile geometry of a batch work item: the run, the tile, its particle
+// slots, and the LDS window (the bounding box of the tile's particles in the
+// previous step, widened by one cell below and two above for the gather and
+// deposit stencils, capped at the allocated window).  All values are
+// wavefront-uniform.  q -> (rz, rx, ry) of a window cell uses the per-tile
+// multipliers m0, m1: floor(q / d) = (q * ceil(2^16 / d)) >> 16 exactly for
+// q < 2^16 / (d - 1), which holds for every window here (at most 2197 cells
+// in 3D, 814 in 2D, divisors at most 37).
+template <int DIM>
+struct TileGeo {
+  int r, tile;
+  unsigned p0, p1;
+  int lo[3], w0[3], Wd[3];
+  unsigned m0, m1;
+  int nwin;
+};
+
+__device__ __forceinline__ unsigned magic16(int d) { return (65536u + (unsigned)d - 1u) / (unsigned)d; }
+
+// window cell q -> (rz, rx, ry)
+template <int DIM>
+__device__ __forceinline__ void win_decode(const TileGeo<DIM>& g, int q, int& rz, int& rx, int& ry) {
+  const int t = (int)(((unsigned)q * g.m0) >> 16);
+  rz = q - t * g.Wd[0];
+  ry = (int)(((unsigned)t * g.m1) >> 16);
+  rx = t - ry * g.Wd[1];
+}
+
+template <int DIM, typename R>
+__device__ __forceinline__ void tile_geo(const BatchTable* __restrict__ bt, long long w, TileGeo<DIM>& g) {
+  using T = Tile<DIM, R>;
+  g.r = __builtin_amdgcn_readfirstlane(locate(bt->pre_tiles, bt->n, w));
+  RunC& rd = *bt->run[g.r];
+  g.tile = (int)(w - bt->pre_tiles[g.r]);
+  const int tz = g.tile % rd.ntz, rest = g.tile / rd.ntz;
+  const int tx = rest % rd.ntx, ty = rest / rd.ntx;
+  const int t0[3] = {tz * T::TZ, tx * T::TX, ty * T::TY};
+  const PIC_C int* ts = ro(rd.tile_start);
+  g.p0 = (unsigned)ts[g.tile];
+  g.p1 = (unsigned)ts[g.tile + 1];
+  const PIC_C Counters& ctr = *ro(rd.ctr);
+  int hi[3] = {T::TZ - 1, T::TX - 1, T::TY - 1};
+  g.lo[0] = g.lo[1] = g.lo[2] = 0;
+  if (!ctr.fresh) {
+    const PIC_C int* bbr = ro(rd.bbox[ctr.bbuf]) + 6 * g.tile;
+    if (bbr[0] <= bbr[3]) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        g.lo[d] = bbr[d];
+        hi[d] = bbr[3 + d];
+      }
+    }
+  }
+  g.Wd[0] = min(hi[0] - g.lo[0] + 4, T::WZ);
+  g.Wd[1] = min(hi[1] - g.lo[1] + 4, T::WX);
+  g.Wd[2] = DIM == 3 ? min(hi[2] - g.lo[2] + 4, T::WY) : 1;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) g.w0[d] = t0[d] + g.lo[d] - 1;
+  if (DIM == 2) g.w0[2] = 0;
+  g.m0 = magic16(g.Wd[0]);
+  g.m1 = magic16(g.Wd[1]);
+  g.nwin = g.Wd[0] * g.Wd[1] * g.Wd[2];
+  // every value is uniform: keep them in scalar registers
+  auto u = [](int v) { return __builtin_amdgcn_readfirstlane(v); };
+  g.tile = u(g.tile);
+  g.p0 = (unsigned)u((int)g.p0);
+  g.p1 = (unsigned)u((int)g.p1);
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    g.lo[d] = u(g.lo[d]);
+    g.w0[d] = u(g.w0[d]);
+    g.Wd[d] = u(g.Wd[d]);
+  }
+  g.m0 = (unsigned)u((int)g.m0);
+  g.m1 = (unsigned)u((int)g.m1);
+  g.nwin = u(g.nwin);
+}
+
+// Issue the global loads of a tile's window of E^n and B^{n-1/2} (NU cells
+// per thread); nothing waits for them here.  zf: bit 0 = the z index is a
+// valid node, bit 1 = a valid half point (open z), sidx = LDS index or -1.
+template <int DIM, typename R, int BLOCK, int NU>
+__device__ __forceinline__ void window_load(const BatchTable* __restrict__ bt, const TileGeo<DIM>& g,
+                                            R (&ld)[NU][6], int (&sidx)[NU], unsigned (&zf)[NU]) {
+  using T = Tile<DIM, R>;
+  RunC& rd = *bt->run[g.r];
+  const int fb = ro(rd.ctr)->fbuf;
+  const Arr3<R> Eg = PIC_ARR3(R, rd.E[fb]);
+  const Arr3<R> Bg = PIC_ARR3(R, rd.B[fb]);
+  const int nx = rd.nx, ny = rd.ny, nz = rd.nz, nzf = rd.nzf;
+  const bool open = rd.open != 0;
+#pragma unroll
+  for (int u = 0; u < NU; ++u) {
+    const int q = threadIdx.x + u * BLOCK;
+    sidx[u] = -1;
+    zf[u] = 0;
+    if (q < g.nwin) {
+      int rz, rx, ry;
+      win_decode(g, q, rz, rx, ry);
+      sidx[u] = (ry * T::WX + rx) * T::WZ + rz;
+      const int gk = g.w0[0] + rz;
+      const int gi = wrap2(g.w0[1] + rx, nx);
+      const int gj = DIM == 3 ? wrap2(g.w0[2] + ry, ny) : 0;
+      int kk;
+      if (open) {
+        zf[u] = (gk >= 0 && gk <= nz ? 1u : 0u) | (gk >= 0 && gk < nz ? 2u : 0u);
+        kk = min(max(gk, 0), nzf - 1);
+      } else {
+        zf[u] = 3u;
+        kk = wrap2(gk, nz);
+      }
+      const long long gq = ((long long)gj * nx + gi) * nzf + kk;
+      ld[u][0] = Eg[0][gq];
+      ld[u][1] = Eg[1][gq];
+      ld[u][2] = Eg[2][gq];
+      ld[u][3] = Bg[0][gq];
+      ld[u][4] = Bg[1][gq];
+      ld[u][5] = Bg[2][gq];
+    }
+  }
+}
+
+// Occupancy of the 3D particle kernel.  Its LDS window (103 KiB in split
+// precision, 107 KiB in FP64) admits one workgroup per CU, so the workgroup
 // is 1024 threads in split precision (16 resident waves per CU, registers
 // capped at 128) and 512 in FP64 (8 waves; the FP64 state needs the
 // registers).  The larger split-precision tile (8x8x8 cells, 8192 particles
@@ -408,6 +530,12 @@ struct PWaves {
   static constexpr int value = DIM == 3 ? (sizeof(R) == 4 ? PIC_WPE3 : PIC_WPE3D) : 1;
 };
 
+// Per tile: store the window (loaded during the previous tile's flush) in
+// LDS, advance B to integer time there, run the tile's particles in chunks
+// of one wavefront taken from a shared counter (so the wavefronts of a
+// workgroup run out of work together), issue the next tile's window loads,
+// reduce the bounding box of the new cells and flush the current window to
+// HBM, zeroing it for the next tile.
 template <int DIM, typename R, int BLOCK, int PUSHER>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(PWaves<DIM, R, BLOCK>::value)))
 void k_particles(const BatchTable* __restrict__ bt) {
@@ -415,131 +543,84 @@ void k_particles(const BatchTable* __restrict__ bt) {
   constexpr int WZM = T::WZ, WXM = T::WX, WYM = T::WY;
   constexpr int WV = WZM * WXM * WYM;
   constexpr int SY = (DIM == 3) ? WZM * WXM : 0;  // LDS stride of y
+  constexpr int NU = (WV + BLOCK - 1) / BLOCK;     // window cells per thread
   // LDS: the current window first, so that every deposit address is one
   // per-particle base plus an immediate offset below 64 KiB
   struct Smem {
     long long J[3][WV];  // Jx Jy Jz, 64-bit fixed point
     R F[6][WV];          // Ex Ey Ez Bx By Bz of the tile window
     int red[6][BLOCK / 64];
+    unsigned next;       // next unclaimed particle chunk of the tile
   };
   __shared__ Smem sm;
   auto& sJ = sm.J;
   auto& sF = sm.F;
   auto& sred = sm.red;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
 
   const XcdSplit xs(bt->tiles);
+  TileGeo<DIM> g;
+  R ld[NU][6];
+  int sidx[NU];
+  unsigned zf[NU];
+  if (xs.beg < xs.end) {
+    tile_geo<DIM, R>(bt, xs.beg, g);
+    if (g.p0 < g.p1) window_load<DIM, R, BLOCK, NU>(bt, g, ld, sidx, zf);
+  }
+  for (int q = threadIdx.x; q < 3 * WV; q += BLOCK) (&sJ[0][0])[q] = 0;
+
   for (long long w = xs.beg; w < xs.end; w += xs.stride) {
-    const int r = __builtin_amdgcn_readfirstlane(locate(bt->pre_tiles, bt->n, w));
-    RunC& rd = *bt->run[r];
-    const int tile = (int)(w - bt->pre_tiles[r]);
-    const PIC_G Counters& ctr = *rd.ctr;
-    const int pb = ctr.pbuf, fb = ctr.fbuf, bb = ctr.bbuf, fresh = ctr.fresh;
+    RunC& rd = *bt->run[g.r];
+    const PIC_C Counters& ctr = *ro(rd.ctr);
+    const int pb = ctr.pbuf, fb = ctr.fbuf, bb = ctr.bbuf;
     const int nx = rd.nx, ny = rd.ny, nz = rd.nz, nzf = rd.nzf;
     const bool open = rd.open != 0;
-
-    const int ntz = rd.ntz, ntx = rd.ntx;
-    const int tz = tile % ntz, rest = tile / ntz;
-    const int tx = rest % ntx, ty = rest / ntx;
-    const int t0[3] = {tz * T::TZ, tx * T::TX, ty * T::TY};
-    const unsigned p0 = (unsigned)rd.tile_start[tile], p1 = (unsigned)rd.tile_start[tile + 1];
-    PIC_G int* bbw = rd.bbox[bb ^ 1] + 6 * tile;
-    if (p0 >= p1) {
+    PIC_G int* bbw = rd.bbox[bb ^ 1] + 6 * g.tile;
+    const long long wn = w + xs.stride;
+    __syncthreads();  // the previous tile's particles and flush are done with the LDS
+    if (g.p0 >= g.p1) {
       if (threadIdx.x == 0) {
         bbw[0] = bbw[1] = bbw[2] = 1 << 20;
         bbw[3] = bbw[4] = bbw[5] = -(1 << 20);
       }
+      if (wn < xs.end) {
+        tile_geo<DIM, R>(bt, wn, g);
+        if (g.p0 < g.p1) window_load<DIM, R, BLOCK, NU>(bt, g, ld, sidx, zf);
+      }
       continue;
     }
-    int lo[3] = {0, 0, 0}, hi[3] = {T::TZ - 1, T::TX - 1, T::TY - 1};
-    if (!fresh) {
-      const PIC_G int* bbr = rd.bbox[bb] + 6 * tile;
-      if (bbr[0] <= bbr[3]) {
-        for (int d = 0; d < 3; ++d) {
-          lo[d] = bbr[d];
-          hi[d] = bbr[3 + d];
-        }
+    const int w00 = g.w0[0], w01 = g.w0[1], w02 = g.w0[2];
+    const int Wd0 = g.Wd[0], Wd1 = g.Wd[1], Wd2 = g.Wd[2];
+    // ---- store the window of E^n and B^{n-1/2} (zero outside an open z range)
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+      const int s = sidx[u];
+      if (s >= 0) {
+        const bool zn = (zf[u] & 1u) != 0, zh = (zf[u] & 2u) != 0;
+        sF[0][s] = zn ? ld[u][0] : R(0);
+        sF[1][s] = zn ? ld[u][1] : R(0);
+        sF[2][s] = zh ? ld[u][2] : R(0);
+        sF[3][s] = zh ? ld[u][3] : R(0);
+        sF[4][s] = zh ? ld[u][4] : R(0);
+        sF[5][s] = zn ? ld[u][5] : R(0);
       }
     }
-    int Wd[3], w0[3];
-    Wd[0] = min(hi[0] - lo[0] + 4, WZM);
-    Wd[1] = min(hi[1] - lo[1] + 4, WXM);
-    Wd[2] = DIM == 3 ? min(hi[2] - lo[2] + 4, WYM) : 1;
-    for (int d = 0; d < 3; ++d) w0[d] = t0[d] + lo[d] - 1;
-    if (DIM == 2) w0[2] = 0;
-
-    const Arr3<R> Eg = PIC_ARR3(R, rd.E[fb]);
-    const Arr3<R> Bg = PIC_ARR3(R, rd.B[fb]);
-    const R dt = R(rd.dt);
-
-    // ---- stage E^n and B^{n-1/2} of the window; clear the current window.
-    // Every thread issues all of its window loads before the first LDS
-    // write, so a tile pays one memory latency instead of one per row.
-    __syncthreads();
-    const int nwin = Wd[0] * Wd[1] * Wd[2];
-    {
-      constexpr int NU = (WV + BLOCK - 1) / BLOCK;
-      R ld[NU][6];
-      int sidx[NU];
-      bool znv[NU], zhv[NU];
-#pragma unroll
-      for (int u = 0; u < NU; ++u) {
-        const int q = threadIdx.x + u * BLOCK;
-        sidx[u] = -1;
-        if (q < nwin) {
-          const int rz = q % Wd[0];
-          const int t = q / Wd[0];
-          const int rx = t % Wd[1], ry = t / Wd[1];
-          sidx[u] = (ry * WXM + rx) * WZM + rz;
-          const int gk = w0[0] + rz;
-          const int gi = wrap2(w0[1] + rx, nx);
-          const int gj = DIM == 3 ? wrap2(w0[2] + ry, ny) : 0;
-          int kk;
-          if (open) {
-            znv[u] = gk >= 0 && gk <= nz;
-            zhv[u] = gk >= 0 && gk < nz;
-            kk = min(max(gk, 0), nzf - 1);
-          } else {
-            znv[u] = zhv[u] = true;
-            kk = wrap2(gk, nz);
-          }
-          const long long g = ((long long)gj * nx + gi) * nzf + kk;
-          ld[u][0] = Eg[0][g];
-          ld[u][1] = Eg[1][g];
-          ld[u][2] = Eg[2][g];
-          ld[u][3] = Bg[0][g];
-          ld[u][4] = Bg[1][g];
-          ld[u][5] = Bg[2][g];
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < NU; ++u) {
-        const int s = sidx[u];
-        if (s >= 0) {
-          sF[0][s] = znv[u] ? ld[u][0] : R(0);
-          sF[1][s] = znv[u] ? ld[u][1] : R(0);
-          sF[2][s] = zhv[u] ? ld[u][2] : R(0);
-          sF[3][s] = zhv[u] ? ld[u][3] : R(0);
-          sF[4][s] = zhv[u] ? ld[u][4] : R(0);
-          sF[5][s] = znv[u] ? ld[u][5] : R(0);
-          sJ[0][s] = 0;
-          sJ[1][s] = 0;
-          sJ[2][s] = 0;
-        }
-      }
-    }
+    if (threadIdx.x == 0) sm.next = 0;
     __syncthreads();
     // ---- B^n = B^{n-1/2} - dt/2 curl E^n on the window (last layer unused)
     {
-      const R hdt = R(0.5) * dt;
+      const R hdt = R(0.5 * rd.dt);
       const R idz = R(1.0 / rd.dz), idx = R(1.0 / rd.dx), idy = DIM == 3 ? R(1.0 / rd.dy) : R(0);
-      const int bz_ = Wd[0] - 1, bx_ = Wd[1] - 1, by_ = DIM == 3 ? Wd[2] - 1 : 1;
+      const int bz_ = Wd0 - 1, bx_ = Wd1 - 1, by_ = DIM == 3 ? Wd2 - 1 : 1;
+      const unsigned mb0 = magic16(bz_), mb1 = magic16(bx_);
       const int nb = bz_ * bx_ * by_;
       for (int q = threadIdx.x; q < nb; q += BLOCK) {
-        const int rz = q % bz_;
-        const int t = q / bz_;
-        const int rx = t % bx_, ry = t / bx_;
+        const int t = (int)(((unsigned)q * mb0) >> 16);
+        const int rz = q - t * bz_;
+        const int ry = (int)(((unsigned)t * mb1) >> 16);
+        const int rx = t - ry * bx_;
         const int s = (ry * WXM + rx) * WZM + rz;
-        const int gk = w0[0] + rz;
+        const int gk = w00 + rz;
         const bool zn = !open || (gk >= 0 && gk <= nz);
         const bool zh = !open || (gk >= 0 && gk < nz);
         const R ex = sF[0][s], ey = sF[1][s], ez = sF[2][s];
@@ -561,11 +642,9 @@ void k_particles(const BatchTable* __restrict__ bt) {
     // tile's first slot (scalar registers) plus one 32-bit byte offset per
     // particle, shared by all of them.  A tile holds far fewer than 2^28
     // particles; one that does not is flagged and left alone.
-    const unsigned nt = p1 - p0;
-    if (nt >= (1u << 28)) {
-      if (threadIdx.x == 0) g_or(&rd.ctr->err, (unsigned)PIC_ERR_TILE);
-      continue;
-    }
+    const unsigned p0 = g.p0, nt = g.p1 - g.p0;
+    bool tile_ok = nt < (1u << 28);
+    if (!tile_ok && threadIdx.x == 0) g_or(&rd.ctr->err, (unsigned)PIC_ERR_TILE);
     PIC_G int* __restrict__ cellp = rd.cell[pb] + p0;
     PIC_G R* __restrict__ o0p = fptr<R>(rd.off[pb][0]) + p0;
     PIC_G R* __restrict__ o1p = fptr<R>(rd.off[pb][1]) + p0;
@@ -577,24 +656,29 @@ void k_particles(const BatchTable* __restrict__ bt) {
     // Window coordinates of a particle are its cell minus the window origin;
     // a periodic correction is needed only where the window crosses the
     // periodic boundary (uniform per tile).  Open z never wraps.
-    const int wrapz = (!open && (w0[0] < 0 || w0[0] + Wd[0] > nz)) ? nz : 0;
-    const int wrapx = (w0[1] < 0 || w0[1] + Wd[1] > nx) ? nx : 0;
-    const int wrapy = (DIM == 3 && (w0[2] < 0 || w0[2] + Wd[2] > ny)) ? ny : 0;
+    const int wrapz = (!open && (w00 < 0 || w00 + Wd0 > nz)) ? nz : 0;
+    const int wrapx = (w01 < 0 || w01 + Wd1 > nx) ? nx : 0;
+    const int wrapy = (DIM == 3 && (w02 < 0 || w02 + Wd2 > ny)) ? ny : 0;
     // bounding box of the new cells, in window coordinates
     int bmin0 = 1 << 20, bmin1 = 1 << 20, bmin2 = 1 << 20;
     int bmax0 = -(1 << 20), bmax1 = -(1 << 20), bmax2 = -(1 << 20);
     bool bad = false;
 
-    // software pipeline: the state of the particles two iterations ahead is
-    // loaded while the current one is advanced (occupancy is set by the LDS
-    // window, so the extra registers are free)
-    unsigned u = threadIdx.x;  // slot relative to the tile's first
-    int cA = -1, cB = -1;
+    // Chunks of 64 consecutive slots are taken from the tile's counter, one
+    // per wavefront and iteration; the state of the next two chunks is
+    // loaded while the current one is advanced (software pipeline).
+    auto grab = [&]() -> unsigned {
+      unsigned v = 0;
+      if (lane == 0) v = atomicAdd(&sm.next, 64u);
+      return __builtin_amdgcn_readfirstlane(v);
+    };
+    unsigned cA = tile_ok ? grab() : nt, cB = tile_ok ? grab() : nt;
+    int sA = -1, sB = -1;
     R oA0 = R(0), oA1 = R(0), oA2 = R(0), uA0 = R(0), uA1 = R(0), uA2 = R(0);
     R oB0 = R(0), oB1 = R(0), oB2 = R(0), uB0 = R(0), uB1 = R(0), uB2 = R(0);
-    if (u < nt) {
-      const unsigned bi = u * 4u, br = u * (unsigned)sizeof(R);
-      cA = at32(cellp, bi);
+    if (cA + lane < nt) {
+      const unsigned u = cA + lane, bi = u * 4u, br = u * (unsigned)sizeof(R);
+      sA = at32(cellp, bi);
       oA0 = at32(o0p, br);
       oA1 = at32(o1p, br);
       if (DIM == 3) oA2 = at32(o2p, br);
@@ -602,9 +686,9 @@ void k_particles(const BatchTable* __restrict__ bt) {
       uA1 = at32(uyp, br);
       uA2 = at32(uzp, br);
     }
-    if (u + BLOCK < nt) {
-      const unsigned bi = (u + BLOCK) * 4u, br = (u + BLOCK) * (unsigned)sizeof(R);
-      cB = at32(cellp, bi);
+    if (cB + lane < nt) {
+      const unsigned u = cB + lane, bi = u * 4u, br = u * (unsigned)sizeof(R);
+      sB = at32(cellp, bi);
       oB0 = at32(o0p, br);
       oB1 = at32(o1p, br);
       if (DIM == 3) oB2 = at32(o2p, br);
@@ -612,21 +696,24 @@ void k_particles(const BatchTable* __restrict__ bt) {
       uB1 = at32(uyp, br);
       uB2 = at32(uzp, br);
     }
-    for (; u < nt; u += BLOCK) {
-      const int c = cA;
+    while (cA < nt) {
+      const unsigned u = cA + lane;  // slot relative to the tile's first
+      const int c = sA;
       R o[3] = {oA0, oA1, oA2};
       R ux = uA0, uy = uA1, uz = uA2;
-      cA = cB;
+      sA = sB;
       oA0 = oB0;
       oA1 = oB1;
       oA2 = oB2;
       uA0 = uB0;
       uA1 = uB1;
       uA2 = uB2;
-      const unsigned un = u + 2 * BLOCK;
-      if (un < nt) {
-        const unsigned bi = un * 4u, br = un * (unsigned)sizeof(R);
-        cB = at32(cellp, bi);
+      cA = cB;
+      cB = grab();
+      sB = -1;
+      if (cB + lane < nt) {
+        const unsigned un = cB + lane, bi = un * 4u, br = un * (unsigned)sizeof(R);
+        sB = at32(cellp, bi);
         oB0 = at32(o0p, br);
         oB1 = at32(o1p, br);
         if (DIM == 3) oB2 = at32(o2p, br);
@@ -634,16 +721,16 @@ void k_particles(const BatchTable* __restrict__ bt) {
         uB1 = at32(uyp, br);
         uB2 = at32(uzp, br);
       }
-      if (c < 0) continue;  // removed
+      if (u >= nt || c < 0) continue;  // past the tile's last slot, or removed
       const int k = cell_k(c), i = cell_i(c), j = DIM == 3 ? cell_j(c) : 0;
-      int wk = k - w0[0], wi = i - w0[1], wj = DIM == 3 ? j - w0[2] : 0;
+      int wk = k - w00, wi = i - w01, wj = DIM == 3 ? j - w02 : 0;
       wk = wrapu(wk, wrapz);
       wi = wrapu(wi, wrapx);
       if (DIM == 3) wj = wrapu(wj, wrapy);
       // the stencil (old cell -1 .. +2) lies in the window: 1 <= w <= Wd - 3
-      const bool fast = (unsigned)(wk - 1) <= (unsigned)(Wd[0] - 4) &&
-                        (unsigned)(wi - 1) <= (unsigned)(Wd[1] - 4) &&
-                        (DIM == 2 || (unsigned)(wj - 1) <= (unsigned)(Wd[2] - 4));
+      const bool fast = (unsigned)(wk - 1) <= (unsigned)(Wd0 - 4) &&
+                        (unsigned)(wi - 1) <= (unsigned)(Wd1 - 4) &&
+                        (DIM == 2 || (unsigned)(wj - 1) <= (unsigned)(Wd2 - 4));
       if (!fast) {
         const unsigned e = g_add(&rd.ctr->n_slowq, 1u);
         if (e < (unsigned long long)rd.capacity) rd.slowq[e] = (int)(p0 + u);
@@ -695,7 +782,6 @@ void k_particles(const BatchTable* __restrict__ bt) {
       bmax1 = max(bmax1, __shfl_xor(bmax1, m));
       bmax2 = max(bmax2, __shfl_xor(bmax2, m));
     }
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     if (lane == 0) {
       sred[0][wave] = bmin0;
       sred[1][wave] = bmin1;
@@ -711,21 +797,32 @@ void k_particles(const BatchTable* __restrict__ bt) {
       for (int q = 1; q < BLOCK / 64; ++q) v = t < 3 ? min(v, sred[t][q]) : max(v, sred[t][q]);
       // window -> tile-relative coordinates (window origin = tile origin + lo - 1)
       const int d = t < 3 ? t : t - 3;
-      if (v != (t < 3 ? (1 << 20) : -(1 << 20))) v += lo[d] - 1;
+      const int lod = d == 0 ? g.lo[0] : (d == 1 ? g.lo[1] : g.lo[2]);  // no dynamic index
+      if (v != (t < 3 ? (1 << 20) : -(1 << 20))) v += lod - 1;
       if (DIM == 2 && (t == 2 || t == 5)) v = 0;
       bbw[t] = v;
     }
-    // ---- flush the current window to HBM
-    for (int q = threadIdx.x; q < nwin; q += BLOCK) {
-      const int rz = q % Wd[0];
-      const int t = q / Wd[0];
-      const int rx = t % Wd[1], ry = t / Wd[1];
+    // ---- the next tile's window loads, in flight during the flush below
+    TileGeo<DIM> gn;
+    gn.p0 = gn.p1 = 0;
+    if (wn < xs.end) {
+      tile_geo<DIM, R>(bt, wn, gn);
+      if (gn.p0 < gn.p1) window_load<DIM, R, BLOCK, NU>(bt, gn, ld, sidx, zf);
+    }
+    // ---- flush the current window to HBM and zero it for the next tile
+    const Arr3<unsigned long long> Jg = PIC_ARR3(unsigned long long, rd.J[fb]);
+    for (int q = threadIdx.x; q < g.nwin; q += BLOCK) {
+      int rz, rx, ry;
+      win_decode(g, q, rz, rx, ry);
       const int s = (ry * WXM + rx) * WZM + rz;
       const long long jx = sJ[0][s], jy = sJ[1][s], jz = sJ[2][s];
       if ((jx | jy | jz) == 0) continue;
-      int gk = w0[0] + rz;
-      const int gi = wrap2(w0[1] + rx, nx);
-      const int gj = DIM == 3 ? wrap2(w0[2] + ry, ny) : 0;
+      sJ[0][s] = 0;
+      sJ[1][s] = 0;
+      sJ[2][s] = 0;
+      int gk = w00 + rz;
+      const int gi = wrap2(w01 + rx, nx);
+      const int gj = DIM == 3 ? wrap2(w02 + ry, ny) : 0;
       bool zn = true, zh = true;
       if (open) {
         zn = gk >= 0 && gk <= nz;
@@ -733,12 +830,12 @@ void k_particles(const BatchTable* __restrict__ bt) {
       } else {
         gk = wrap2(gk, nz);
       }
-      const long long g = ((long long)gj * nx + gi) * nzf + gk;
-      const Arr3<unsigned long long> Jg = PIC_ARR3(unsigned long long, rd.J[fb]);
-      if (zn && jx != 0) g_add(Jg[0] + g, (unsigned long long)jx);
-      if (zn && jy != 0) g_add(Jg[1] + g, (unsigned long long)jy);
-      if (zh && jz != 0) g_add(Jg[2] + g, (unsigned long long)jz);
+      const long long gq = ((long long)gj * nx + gi) * nzf + gk;
+      if (zn && jx != 0) g_add(Jg[0] + gq, (unsigned long long)jx);
+      if (zn && jy != 0) g_add(Jg[1] + gq, (unsigned long long)jy);
+      if (zh && jz != 0) g_add(Jg[2] + gq, (unsigned long long)jz);
     }
+    g = gn;
   }
 }
 

@@ -262,6 +262,7 @@ struct pic_run {
   BatchTable* dtabB;
   BatchTable htab1;
   BatchTable htabB;
+  Counters hctr0;  // initial device counters (host staging of the asynchronous init)
   int ncu, gpart, ggen;
   bool use_graph;
   hipGraphExec_t g1[2];  // one single-run step: [1] with the sort chain, [0] without
@@ -597,7 +598,9 @@ pic_status pic_init_boosted(const pic_lab_params* p, void* dev_buf, size_t bytes
   r->dtabB = at<BatchTable>(r, L.tabB);
   h.ctr = r->dctr;
 
-  Counters c0;
+  // host staging of the copies below lives in the run handle (hrd, hctr0,
+  // htab1), so the copies may still be in flight when this call returns
+  Counters& c0 = r->hctr0;
   memset(&c0, 0, sizeof(c0));
   c0.last_sort = -1;
   pic_run* self = r;
@@ -605,6 +608,7 @@ pic_status pic_init_boosted(const pic_lab_params* p, void* dev_buf, size_t bytes
 
   hipStream_t s = r->stream;
   auto bail = [&](pic_status e) {
+    (void)hipStreamSynchronize(s);  // nothing enqueued may still read the handle
     delete r;
     return e;
   };
@@ -626,7 +630,6 @@ pic_status pic_init_boosted(const pic_lab_params* p, void* dev_buf, size_t bytes
   launch_rho(r->p.dims, r->p.precision, r->drd, at<double>(r, L.rho_a), d.npts, d.capacity, 0, s);
   launch_gauss(r->p.precision, r->drd, d.npts, 0, gauss_rho(r), s);
   INITCHK(hipGetLastError());
-  INITCHK(hipStreamSynchronize(s));
 #undef INITCHK
   *out = r;
   return PIC_OK;
@@ -946,6 +949,8 @@ pic_status pic_get_derived(const pic_run* r, pic_derived* o) {
 
 pic_status pic_free(pic_run* r) {
   if (!r) return PIC_OK;
+  // work still queued on the run's stream may read the handle's host staging
+  (void)hipStreamSynchronize(r->stream);
   for (int q = 0; q < 2; ++q) {
     if (r->g1[q]) (void)hipGraphExecDestroy(r->g1[q]);
     if (r->gB[q]) (void)hipGraphExecDestroy(r->gB[q]);

@@ -40,15 +40,18 @@ constexpr unsigned DEAD = 0x80000000u;
 
 // Tile geometry (cells) and the largest LDS window a tile may use.  The
 // window spans the tile's particle bounding box widened by one cell below
-// and two above (gather and deposit stencils): W = extent + 3, plus one cell
-// of slack for the fractional drift of the plasma between two sorts in z.
-// 3D split precision: 8x8x8 cells, a 14x13x13 window of 111 KiB (one
-// 1024-thread workgroup per CU); 3D FP64: 8x8x4 cells, 14x13x9, 115 KiB.
+// and two above (gather and deposit stencils): W = extent + 3, so a tile's
+// particles may spread over TZ + 2 cells in z and TX + 2, TY + 2 across.
+// The z extent W_z = 13 is odd: the LDS word offsets of the cells of an
+// 8x8 transverse plane (x stride 13, y stride 169) then fall in distinct
+// banks, where with 14 they all are even (two lanes per bank).
+// 3D split precision: 8x8x8 cells, a 13x13x13 window of 103 KiB (one
+// 1024-thread workgroup per CU); 3D FP64: 8x8x4 cells, 13x13x9, 107 KiB.
 template <int DIM, typename R> struct Tile;
 template <typename R> struct Tile<3, R> {
   static constexpr int LZ = 3, LX = 3, LY = sizeof(R) == 4 ? 3 : 2;
   static constexpr int TZ = 1 << LZ, TX = 1 << LX, TY = 1 << LY;
-  static constexpr int WZ = TZ + 6, WX = TX + 5, WY = TY + 5;
+  static constexpr int WZ = TZ + 5, WX = TX + 5, WY = TY + 5;
 };
 // 2D: 16x16 cells, a 22x37 window (39 KiB; four 256-thread workgroups per
 // CU): 21 cells of transverse slack, because electrons quivering in a
@@ -319,6 +322,16 @@ __device__ __forceinline__ bool sort_due(const PIC_G Counters& c, int every) {
 }
 
 template <typename R> __device__ __forceinline__ PIC_G R* fptr(PIC_G void* p) { return (PIC_G R*)p; }
+
+// Read-only view of global memory that no kernel writes while the caller
+// runs (tile starts, the previous step's bounding boxes, buffer parities):
+// through the constant address space, uniform reads become scalar loads,
+// which wait on their own counter instead of on every outstanding vector
+// memory operation.
+template <typename T>
+__device__ __forceinline__ const PIC_C T* ro(const PIC_G T* p) {
+  return (const PIC_C T*)(size_t)p;
+}
 
 // element at byte offset b (32-bit, zero-extended) from a global base: the
 // base stays in scalar registers and the offset in one vector register

@@ -214,13 +214,28 @@ def test_batched_runs_equal_alone():
         r.close()
 
 
-def test_no_plasma_and_no_laser_edge_cases():
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-5)])
+def test_vacuum_laser_against_the_oracle(prec, tol):
+    """No plasma (ppc = 0): the boosted laser alone propagates through the
+    Yee grid and out through the Mur ends; fields and the diagnostics match
+    the oracle's."""
     cfg = workloads.config("c1", nz=32, nx=16, ppc=0)
-    r = pic.Run(cfg, "fp32")
-    r.step(5)
-    d = r.diag()
-    assert d["n_particles"] == 0 and d["U_E"] > 0
+    r = pic.Run(cfg, prec)
+    st = oracle.State(cfg)
+    r.step(25)
+    st.step(25)
+    assert _field_relerr(r, st) < tol
+    d, do = r.diag(), st.diag()
+    assert d["n_particles"] == 0 == do["n_particles"]
+    assert d["KE"] == 0.0
+    for k in ("U_E", "U_B", "Ez_max"):
+        assert d[k] == pytest.approx(do[k], rel=10 * tol, abs=1e-300)
+    assert do["U_E"] > 0
     r.close()
+    st.close()
+
+
+def test_no_plasma_and_no_laser_edge_cases():
     cfg = workloads.config("c1", nz=32, nx=16, a0=0.0)
     r = pic.Run(cfg, "fp32")
     st = oracle.State(cfg, round_f32=True)
