@@ -113,15 +113,38 @@ __device__ __forceinline__ Dep1<R> dep1(R o0, R o1, int carry) {
   return d;
 }
 
-// offset carry after a move of less than one cell (CFL)
-// (selects only: a branch per dimension costs more than the arithmetic)
+// Esirkepov shape data along a dimension in which no lane of the wavefront
+// crossed a cell boundary: the window is the particle's own two nodes.  The
+// values are rounded exactly as dep1 rounds them for a particle that stays,
+// so a particle's current does not depend on the other lanes of its
+// wavefront.
+template <typename R>
+__device__ __forceinline__ Dep1<R> dep1_stay(R o0, R o1) {
+  Dep1<R> d;
+  const R a0 = R(1) - o0;
+  d.S0[0] = a0;
+  d.S0[1] = o0;
+  d.S0[2] = R(0);
+  d.DS[0] = (R(1) - o1) - a0;
+  d.DS[1] = o1 - o0;
+  d.DS[2] = R(0);
+  d.P[0] = o0 - o1;
+  d.P[1] = R(0);
+  d.base = 0;
+  return d;
+}
+
+// offset carry after a move of less than one cell (CFL): o in (-1, 2) ->
+// carry floor(o) in {-1, 0, 1} and offset o - floor(o), which is exact for
+// o >= 0 and rounded for o < 0; when o + 1 rounds to 1 the particle stays
+// in its cell at offset 0
 template <typename R>
 __device__ __forceinline__ int carry(R& o) {
-  const int c = (int)(o >= R(1)) - (int)(o < R(0));
-  const R on = o - R(c);
-  const bool up1 = c < 0 && on >= R(1);  // o + 1 rounded up to 1: stay in the cell at offset 0
+  const R f = floor(o);
+  const R on = o - f;
+  const bool up1 = on == R(1);
   o = up1 ? R(0) : on;
-  return up1 ? 0 : c;
+  return (int)f + (up1 ? 1 : 0);
 }
 
 // A current contribution x, already in fixed-point units, as a 64-bit
@@ -227,23 +250,41 @@ __device__ __forceinline__ void dep2(const Dep1<R>& Z, const Dep1<R>& X, R cz, R
   }
 }
 
-template <int DIM, typename R, class A>
-__device__ __forceinline__ void deposit(const Dep1<R>* d, const int* cr, R cz, R cx, R cy, R cyv, A&& add) {
+// The deposit of one particle, in the variant of its wavefront: the shape
+// data across x and y are those of a 3-node window where some lane of the
+// wavefront crossed a cell boundary in that dimension, else of the
+// particle's own two nodes.  adder(zb, xb, yb) gives the accumulator of the
+// window that starts at (zb, xb, yb) from the old cell.
+template <int DIM, typename R, class AF>
+__device__ __forceinline__ void deposit(const Dep1<R>& Z, const R* o, const R* on, const int* cr, R cz, R cx,
+                                        R cy, R cyv, AF&& adder) {
   // wavefront-uniform: does any active lane cross a cell boundary in x, in y?
   if constexpr (DIM == 3) {
     const bool ax = __any(cr[1] != 0), ay = __any(cr[2] != 0);
     if (ax) {
-      if (ay) dep3<R, 3, 3>(d[0], d[1], d[2], cz, cx, cy, add);
-      else dep3<R, 3, 2>(d[0], d[1], d[2], cz, cx, cy, add);
+      const Dep1<R> X = dep1(o[1], on[1], cr[1]);
+      if (ay) {
+        const Dep1<R> Y = dep1(o[2], on[2], cr[2]);
+        dep3<R, 3, 3>(Z, X, Y, cz, cx, cy, adder(Z.base, X.base, Y.base));
+      } else {
+        dep3<R, 3, 2>(Z, X, dep1_stay(o[2], on[2]), cz, cx, cy, adder(Z.base, X.base, 0));
+      }
     } else {
-      if (ay) dep3<R, 2, 3>(d[0], d[1], d[2], cz, cx, cy, add);
-      else dep3<R, 2, 2>(d[0], d[1], d[2], cz, cx, cy, add);
+      const Dep1<R> X = dep1_stay(o[1], on[1]);
+      if (ay) {
+        const Dep1<R> Y = dep1(o[2], on[2], cr[2]);
+        dep3<R, 2, 3>(Z, X, Y, cz, cx, cy, adder(Z.base, 0, Y.base));
+      } else {
+        dep3<R, 2, 2>(Z, X, dep1_stay(o[2], on[2]), cz, cx, cy, adder(Z.base, 0, 0));
+      }
     }
   } else {
-    if (__any(cr[1] != 0))
-      dep2<R, 3>(d[0], d[1], cz, cx, cyv, add);
-    else
-      dep2<R, 2>(d[0], d[1], cz, cx, cyv, add);
+    if (__any(cr[1] != 0)) {
+      const Dep1<R> X = dep1(o[1], on[1], cr[1]);
+      dep2<R, 3>(Z, X, cz, cx, cyv, adder(Z.base, X.base, 0));
+    } else {
+      dep2<R, 2>(Z, dep1_stay(o[1], on[1]), cz, cx, cyv, adder(Z.base, 0, 0));
+    }
   }
 }
 
@@ -355,28 +396,34 @@ __device__ __forceinline__ bool advance(const PConst<R>& K, R* o, R& ux, R& uy, 
   cr[0] = carry(on[0]);
   cr[1] = carry(on[1]);
   cr[2] = DIM == 3 ? carry(on[2]) : 0;
-  Dep1<R> dd[3];
-  dd[0] = dep1(o[0], on[0], cr[0]);
-  dd[1] = dep1(o[1], on[1], cr[1]);
-  if (DIM == 3) dd[2] = dep1(o[2], on[2], cr[2]);
-  deposit<DIM, R>(dd, cr, K.cz, K.cx, K.cy, K.cyv * (uy * ig),
-                  adder(dd[0].base, dd[1].base, DIM == 3 ? dd[2].base : 0));
+  deposit<DIM, R>(dep1(o[0], on[0], cr[0]), o, on, cr, K.cz, K.cx, K.cy, K.cyv * (uy * ig), adder);
   o[0] = on[0];
   o[1] = on[1];
   o[2] = on[2];
   return bad;
 }
 
-// new packed cell after the carries; removal at the open z ends
+// new packed cell after the carries; removal at the open z ends.  wrap =
+// false (uniform) when no particle of the tile can cross a periodic
+// boundary: the carries are then added to the packed fields directly.
 template <int DIM>
-__device__ __forceinline__ int new_cell(RunC& rd, int k, int i, int j, const int* cr, bool& dead,
-                                        int& k1, int& i1, int& j1) {
+__device__ __forceinline__ int new_cell(RunC& rd, int c, int k, int i, int j, const int* cr, bool wrap,
+                                        bool& dead, int& k1, int& i1, int& j1) {
   const bool open = rd.open != 0;
-  k1 = wrapu(k + cr[0], open ? 0 : rd.nz);
-  i1 = wrapu(i + cr[1], rd.nx);
-  j1 = DIM == 3 ? wrapu(j + cr[2], rd.ny) : 0;
+  int nc;
+  if (wrap) {
+    k1 = wrapu(k + cr[0], open ? 0 : rd.nz);
+    i1 = wrapu(i + cr[1], rd.nx);
+    j1 = DIM == 3 ? wrapu(j + cr[2], rd.ny) : 0;
+    nc = cell_pack(k1, i1, j1);
+  } else {
+    k1 = k + cr[0];
+    i1 = i + cr[1];
+    j1 = DIM == 3 ? j + cr[2] : 0;
+    nc = c + cr[0] + (cr[1] << KBITS) + (DIM == 3 ? cr[2] << (KBITS + IBITS) : 0);
+  }
   dead = open && (unsigned)k1 >= (unsigned)rd.ztop;  // left through z = 0 or beyond ztop
-  return cell_pack(k1, i1, j1) | (dead ? (int)DEAD : 0);
+  return nc | (dead ? (int)DEAD : 0);
 }
 
 // Per-tile geometry of a batch work item: the run, the tile, its particle
@@ -478,7 +525,7 @@ __device__ __forceinline__ void window_load(const BatchTable* __restrict__ bt, c
     if (q < g.nwin) {
       int rz, rx, ry;
       win_decode(g, q, rz, rx, ry);
-      sidx[u] = (ry * T::WX + rx) * T::WZ + rz;
+      sidx[u] = ry * (DIM == 3 ? T::SY : 0) + rx * T::WZ + rz;
       const int gk = g.w0[0] + rz;
       const int gi = wrap2(g.w0[1] + rx, nx);
       const int gj = DIM == 3 ? wrap2(g.w0[2] + ry, ny) : 0;
@@ -541,22 +588,22 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(PWaves<DI
 void k_particles(const BatchTable* __restrict__ bt) {
   using T = Tile<DIM, R>;
   constexpr int WZM = T::WZ, WXM = T::WX, WYM = T::WY;
-  constexpr int WV = WZM * WXM * WYM;
-  constexpr int SY = (DIM == 3) ? WZM * WXM : 0;  // LDS stride of y
-  constexpr int NU = (WV + BLOCK - 1) / BLOCK;     // window cells per thread
+  constexpr int SY = (DIM == 3) ? T::SY : 0;              // LDS stride of y
+  constexpr int WV = (DIM == 3) ? SY * WYM : WZM * WXM;  // LDS stride of a component
+  constexpr int NU = (WZM * WXM * WYM + BLOCK - 1) / BLOCK;  // window cells per thread
+  static_assert(3 * WV * 8 <= 65536, "deposit offsets must fit the 16-bit LDS offset");
   // LDS: the current window first, so that every deposit address is one
   // per-particle base plus an immediate offset below 64 KiB
   struct Smem {
     long long J[3][WV];  // Jx Jy Jz, 64-bit fixed point
     R F[6][WV];          // Ex Ey Ez Bx By Bz of the tile window
-    int red[6][BLOCK / 64];
+    int bb[6];           // bounding box of the new cells (window coordinates)
     unsigned next;       // next unclaimed particle chunk of the tile
   };
   __shared__ Smem sm;
   auto& sJ = sm.J;
   auto& sF = sm.F;
-  auto& sred = sm.red;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int lane = threadIdx.x & 63;
 
   const XcdSplit xs(bt->tiles);
   TileGeo<DIM> g;
@@ -606,6 +653,7 @@ void k_particles(const BatchTable* __restrict__ bt) {
       }
     }
     if (threadIdx.x == 0) sm.next = 0;
+    if (threadIdx.x < 6) sm.bb[threadIdx.x] = threadIdx.x < 3 ? (1 << 20) : -(1 << 20);
     __syncthreads();
     // ---- B^n = B^{n-1/2} - dt/2 curl E^n on the window (last layer unused)
     {
@@ -619,7 +667,7 @@ void k_particles(const BatchTable* __restrict__ bt) {
         const int rz = q - t * bz_;
         const int ry = (int)(((unsigned)t * mb1) >> 16);
         const int rx = t - ry * bx_;
-        const int s = (ry * WXM + rx) * WZM + rz;
+        const int s = ry * SY + rx * WZM + rz;
         const int gk = w00 + rz;
         const bool zn = !open || (gk >= 0 && gk <= nz);
         const bool zh = !open || (gk >= 0 && gk < nz);
@@ -659,23 +707,27 @@ void k_particles(const BatchTable* __restrict__ bt) {
     const int wrapz = (!open && (w00 < 0 || w00 + Wd0 > nz)) ? nz : 0;
     const int wrapx = (w01 < 0 || w01 + Wd1 > nx) ? nx : 0;
     const int wrapy = (DIM == 3 && (w02 < 0 || w02 + Wd2 > ny)) ? ny : 0;
+    // a particle can cross a periodic boundary only in a tile whose window
+    // (its cells -1 .. +2) crosses it
+    const bool wrapany = (wrapz | wrapx | wrapy) != 0;
     // bounding box of the new cells, in window coordinates
     int bmin0 = 1 << 20, bmin1 = 1 << 20, bmin2 = 1 << 20;
     int bmax0 = -(1 << 20), bmax1 = -(1 << 20), bmax2 = -(1 << 20);
     bool bad = false;
 
     // Chunks of 64 consecutive slots are taken from the tile's counter, one
-    // per wavefront and iteration; the state of the next two chunks is
-    // loaded while the current one is advanced (software pipeline).
+    // per wavefront and iteration; the state of the next chunk is loaded
+    // while the current one is advanced (software pipeline).  Only one chunk
+    // is held ahead, so the wavefronts run out of work within one iteration
+    // of each other.
     auto grab = [&]() -> unsigned {
       unsigned v = 0;
       if (lane == 0) v = atomicAdd(&sm.next, 64u);
       return __builtin_amdgcn_readfirstlane(v);
     };
-    unsigned cA = tile_ok ? grab() : nt, cB = tile_ok ? grab() : nt;
-    int sA = -1, sB = -1;
+    unsigned cA = tile_ok ? grab() : nt;
+    int sA = -1;
     R oA0 = R(0), oA1 = R(0), oA2 = R(0), uA0 = R(0), uA1 = R(0), uA2 = R(0);
-    R oB0 = R(0), oB1 = R(0), oB2 = R(0), uB0 = R(0), uB1 = R(0), uB2 = R(0);
     if (cA + lane < nt) {
       const unsigned u = cA + lane, bi = u * 4u, br = u * (unsigned)sizeof(R);
       sA = at32(cellp, bi);
@@ -686,47 +738,31 @@ void k_particles(const BatchTable* __restrict__ bt) {
       uA1 = at32(uyp, br);
       uA2 = at32(uzp, br);
     }
-    if (cB + lane < nt) {
-      const unsigned u = cB + lane, bi = u * 4u, br = u * (unsigned)sizeof(R);
-      sB = at32(cellp, bi);
-      oB0 = at32(o0p, br);
-      oB1 = at32(o1p, br);
-      if (DIM == 3) oB2 = at32(o2p, br);
-      uB0 = at32(uxp, br);
-      uB1 = at32(uyp, br);
-      uB2 = at32(uzp, br);
-    }
     while (cA < nt) {
       const unsigned u = cA + lane;  // slot relative to the tile's first
       const int c = sA;
       R o[3] = {oA0, oA1, oA2};
       R ux = uA0, uy = uA1, uz = uA2;
-      sA = sB;
-      oA0 = oB0;
-      oA1 = oB1;
-      oA2 = oB2;
-      uA0 = uB0;
-      uA1 = uB1;
-      uA2 = uB2;
-      cA = cB;
-      cB = grab();
-      sB = -1;
-      if (cB + lane < nt) {
-        const unsigned un = cB + lane, bi = un * 4u, br = un * (unsigned)sizeof(R);
-        sB = at32(cellp, bi);
-        oB0 = at32(o0p, br);
-        oB1 = at32(o1p, br);
-        if (DIM == 3) oB2 = at32(o2p, br);
-        uB0 = at32(uxp, br);
-        uB1 = at32(uyp, br);
-        uB2 = at32(uzp, br);
+      cA = grab();
+      sA = -1;
+      if (cA + lane < nt) {
+        const unsigned un = cA + lane, bi = un * 4u, br = un * (unsigned)sizeof(R);
+        sA = at32(cellp, bi);
+        oA0 = at32(o0p, br);
+        oA1 = at32(o1p, br);
+        if (DIM == 3) oA2 = at32(o2p, br);
+        uA0 = at32(uxp, br);
+        uA1 = at32(uyp, br);
+        uA2 = at32(uzp, br);
       }
       if (u >= nt || c < 0) continue;  // past the tile's last slot, or removed
       const int k = cell_k(c), i = cell_i(c), j = DIM == 3 ? cell_j(c) : 0;
       int wk = k - w00, wi = i - w01, wj = DIM == 3 ? j - w02 : 0;
-      wk = wrapu(wk, wrapz);
-      wi = wrapu(wi, wrapx);
-      if (DIM == 3) wj = wrapu(wj, wrapy);
+      if (wrapany) {
+        wk = wrapu(wk, wrapz);
+        wi = wrapu(wi, wrapx);
+        if (DIM == 3) wj = wrapu(wj, wrapy);
+      }
       // the stencil (old cell -1 .. +2) lies in the window: 1 <= w <= Wd - 3
       const bool fast = (unsigned)(wk - 1) <= (unsigned)(Wd0 - 4) &&
                         (unsigned)(wi - 1) <= (unsigned)(Wd1 - 4) &&
@@ -736,7 +772,7 @@ void k_particles(const BatchTable* __restrict__ bt) {
         if (e < (unsigned long long)rd.capacity) rd.slowq[e] = (int)(p0 + u);
         continue;
       }
-      const int base = (wj * WXM + wi) * WZM + wk;
+      const int base = wj * SY + wi * WZM + wk;
       int cr[3];
       bad |= advance<DIM, R, PUSHER>(
           K, o, ux, uy, uz, cr,
@@ -750,7 +786,7 @@ void k_particles(const BatchTable* __restrict__ bt) {
       bool dead;
       int k1, i1, j1;
       const unsigned bi = u * 4u, br = u * (unsigned)sizeof(R);
-      at32(cellp, bi) = new_cell<DIM>(rd, k, i, j, cr, dead, k1, i1, j1);
+      at32(cellp, bi) = new_cell<DIM>(rd, c, k, i, j, cr, wrapany, dead, k1, i1, j1);
       at32(o0p, br) = o[0];
       at32(o1p, br) = o[1];
       if (DIM == 3) at32(o2p, br) = o[2];
@@ -783,18 +819,17 @@ void k_particles(const BatchTable* __restrict__ bt) {
       bmax2 = max(bmax2, __shfl_xor(bmax2, m));
     }
     if (lane == 0) {
-      sred[0][wave] = bmin0;
-      sred[1][wave] = bmin1;
-      sred[2][wave] = bmin2;
-      sred[3][wave] = bmax0;
-      sred[4][wave] = bmax1;
-      sred[5][wave] = bmax2;
+      atomicMin(&sm.bb[0], bmin0);
+      atomicMin(&sm.bb[1], bmin1);
+      atomicMin(&sm.bb[2], bmin2);
+      atomicMax(&sm.bb[3], bmax0);
+      atomicMax(&sm.bb[4], bmax1);
+      atomicMax(&sm.bb[5], bmax2);
     }
     __syncthreads();
     if (threadIdx.x < 6) {
       const int t = threadIdx.x;
-      int v = sred[t][0];
-      for (int q = 1; q < BLOCK / 64; ++q) v = t < 3 ? min(v, sred[t][q]) : max(v, sred[t][q]);
+      int v = sm.bb[t];
       // window -> tile-relative coordinates (window origin = tile origin + lo - 1)
       const int d = t < 3 ? t : t - 3;
       const int lod = d == 0 ? g.lo[0] : (d == 1 ? g.lo[1] : g.lo[2]);  // no dynamic index
@@ -814,7 +849,7 @@ void k_particles(const BatchTable* __restrict__ bt) {
     for (int q = threadIdx.x; q < g.nwin; q += BLOCK) {
       int rz, rx, ry;
       win_decode(g, q, rz, rx, ry);
-      const int s = (ry * WXM + rx) * WZM + rz;
+      const int s = ry * SY + rx * WZM + rz;
       const long long jx = sJ[0][s], jy = sJ[1][s], jz = sJ[2][s];
       if ((jx | jy | jz) == 0) continue;
       sJ[0][s] = 0;
@@ -906,7 +941,7 @@ __global__ __launch_bounds__(256) void k_particles_hbm(const BatchTable* __restr
       if (bad) g_or(&rd.ctr->err, 1u);
       bool dead;
       int k1, i1, j1;
-      rd.cell[pb][p] = new_cell<DIM>(rd, k, i, j, cr, dead, k1, i1, j1);
+      rd.cell[pb][p] = new_cell<DIM>(rd, c, k, i, j, cr, true, dead, k1, i1, j1);
       fptr<R>(rd.off[pb][0])[p] = o[0];
       fptr<R>(rd.off[pb][1])[p] = o[1];
       if (DIM == 3) fptr<R>(rd.off[pb][2])[p] = o[2];
@@ -1308,8 +1343,8 @@ int grid_particles(int dims, int prec, int ncu) {
   const size_t per_cell = 6 * sizeof(float) * (prec ? 2 : 1) + 3 * sizeof(long long);
   size_t lds;
   if (dims == 3)
-    lds = prec ? per_cell * Tile<3, double>::WZ * Tile<3, double>::WX * Tile<3, double>::WY
-               : per_cell * Tile<3, float>::WZ * Tile<3, float>::WX * Tile<3, float>::WY;
+    lds = prec ? per_cell * Tile<3, double>::SY * Tile<3, double>::WY
+               : per_cell * Tile<3, float>::SY * Tile<3, float>::WY;
   else
     lds = per_cell * Tile<2, float>::WZ * Tile<2, float>::WX;
   int per_cu = (int)((160 * 1024) / (lds + 1024));

@@ -45,13 +45,20 @@ constexpr unsigned DEAD = 0x80000000u;
 // The z extent W_z = 13 is odd: the LDS word offsets of the cells of an
 // 8x8 transverse plane (x stride 13, y stride 169) then fall in distinct
 // banks, where with 14 they all are even (two lanes per bank).
-// 3D split precision: 8x8x8 cells, a 13x13x13 window of 103 KiB (one
-// 1024-thread workgroup per CU); 3D FP64: 8x8x4 cells, 13x13x9, 107 KiB.
+// 3D split precision: 8x8x8 cells, a 13x13x13 window (y stride padded to
+// 200 cells) of 122 KiB (one 1024-thread workgroup per CU); 3D FP64: 8x8x4
+// cells, 13x13x9, 107 KiB.
 template <int DIM, typename R> struct Tile;
 template <typename R> struct Tile<3, R> {
   static constexpr int LZ = 3, LX = 3, LY = sizeof(R) == 4 ? 3 : 2;
   static constexpr int TZ = 1 << LZ, TX = 1 << LX, TY = 1 << LY;
   static constexpr int WZ = TZ + 5, WX = TX + 5, WY = TY + 5;
+  // LDS stride of y.  In split precision it is padded from WZ WX to the next
+  // value = 8 (mod 64): with the odd x stride WZ, the word offsets
+  // WZ i + SY j of an 8x8 transverse plane (the cells of one wavefront's
+  // lanes) are then 64 distinct banks, so a pair read (z, z+1) or a 64-bit
+  // atomic loads every bank exactly twice (unpadded: up to four times).
+  static constexpr int SY = sizeof(R) == 4 ? WZ * WX + ((8 - WZ * WX) % 64 + 64) % 64 : WZ * WX;
 };
 // 2D: 16x16 cells, a 22x37 window (39 KiB; four 256-thread workgroups per
 // CU): 21 cells of transverse slack, because electrons quivering in a
@@ -63,6 +70,7 @@ template <typename R> struct Tile<2, R> {
   static constexpr int LZ = 4, LX = 4, LY = 0;
   static constexpr int TZ = 1 << LZ, TX = 1 << LX, TY = 1;
   static constexpr int WZ = TZ + 6, WX = TX + 21, WY = 1;
+  static constexpr int SY = 0;  // no y
 };
 
 // Yee staggering per component (half-cell flags in z, x, y):
