@@ -8,14 +8,23 @@
 // Maxwellian momenta boosted to the frame: Sec. 2, second paragraph - the
 // plasma is denser and drifting in the boosted frame), appending them after
 // the current slots; (2) count live particles per tile; (3) exclusive scan of
-// the counts (one workgroup per run); (4) scatter into the other particle
-// buffer, which also drops removed particles; (5) commit the new counts and
-// flip the buffer.  Per-tile atomics are aggregated over the wavefront with
-// ballots: lanes with equal keys elect a leader that makes one atomic add,
-// and each lane's rank inside its group is a popcount of the lower lanes, so
-// a wavefront's particles keep their relative order in the destination
-// (consecutive particles stay in different cells, which keeps the LDS
-// current atomics of the step kernel free of same-address conflicts).
+// the counts, each tile's range padded to a multiple of 64 slots with
+// removed markers (one workgroup per run); (4) scatter into the other
+// particle buffer, which also drops removed particles; (5) commit the new
+// counts and flip the buffer.
+// Wavefront groups.  The injection creates the plasma in groups of 64
+// consecutive slots that lie in 64 different cells of one tile's transverse
+// plane, and the step kernel gives each wavefront 64 consecutive slots of a
+// tile starting at a multiple of 64; when the two coincide, the lanes of a
+// wavefront add their currents to 64 different LDS cells that fall in
+// distinct banks.  The sort keeps them coinciding: a source wavefront whose
+// 64 slots are live and go to one tile (a whole group) is placed at the
+// tile's front cursor, which advances by 64, and the particles of the other
+// source wavefronts (groups split by a tile boundary, removed particles)
+// follow behind the whole groups.  Per-tile atomics of those are aggregated
+// over the wavefront with ballots: lanes with equal keys elect a leader that
+// makes one atomic add, and each lane's rank inside its group is a popcount
+// of the lower lanes.
 #include <hip/hip_runtime.h>
 
 #include "launch.hpp"
@@ -89,6 +98,33 @@ __device__ __forceinline__ void wave_agg_count(PIC_G int* base, int key, bool ac
     if (lane == leader) (void)g_add(base + lkey, (int)__popcll(m));
     pend &= ~m;
   }
+}
+
+// Sort key of the particles of one source wavefront (uniform decision).
+// The wavefront is a whole group if its 64 slots are live, span at most
+// GZ + 1 consecutive z cells (two in split precision, where a group is one
+// column; more where it interleaves columns) and lie in one tile's
+// transverse range: all of them then go to the tile of the group's lowest
+// cell, so the drift of the plasma never splits a group at a tile boundary
+// (the upper members may sit up to GZ cells above the tile's z range; the
+// step kernel's window covers them).
+// Otherwise every particle goes to the tile of its own cell.
+template <int DIM, typename R>
+__device__ __forceinline__ int sort_key(RunC& rd, int cc, bool act, bool& whole) {
+  using T = Tile<DIM, R>;
+  const int own = act ? tile_of<DIM, R>(rd, cc) : 0;
+  whole = false;
+  if (__ballot(act) != ~0ull) return own;
+  int kmin = cell_k(cc), kmax = kmin;
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    kmin = min(kmin, __shfl_xor(kmin, m));
+    kmax = max(kmax, __shfl_xor(kmax, m));
+  }
+  if (kmax - kmin > T::GZ) return own;
+  const int key = own - ((cell_k(cc) >> T::LZ) - (kmin >> T::LZ));  // tiles are z-fastest
+  whole = __ballot(key == __shfl(key, 0)) == ~0ull;
+  return whole ? key : own;
 }
 
 // The work items of the runs that sort at this step, as one flat range:
@@ -276,8 +312,16 @@ __global__ __launch_bounds__(256) void k_count(const BatchTable* __restrict__ bt
       int cc = -1;
       if (q < total) cc = cellp[q];
       const bool act = cc >= 0;
-      const int key = act ? tile_of<DIM, R>(rd, cc) : 0;
-      wave_agg_count(rd.tile_count, key, act);
+      bool whole;
+      const int key = sort_key<DIM, R>(rd, cc, act, whole);
+      if (whole) {
+        if ((threadIdx.x & 63) == 0) {
+          (void)g_add(rd.tile_count + key, 64);
+          (void)g_add(rd.tile_full + key, 64);
+        }
+      } else {
+        wave_agg_count(rd.tile_count, key, act);
+      }
     }
   }
 }
@@ -288,16 +332,22 @@ __global__ __launch_bounds__(1024) void k_scan(const BatchTable* __restrict__ bt
   RunC& rd = *bt->run[blockIdx.x];
   PIC_G Counters* c = rd.ctr;
   if (!sort_due(*c, rd.inject_every)) return;
-  __shared__ int wsum[16];
+  __shared__ int wsum[16], lsum[16];
   __shared__ int carry_s;
   const int n = rd.ntiles;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int per = (n + 1023) / 1024;
   const int beg = threadIdx.x * per;
-  int sum = 0;
+  // tile t occupies pad64(count) slots
+  auto pad64 = [](int v) { return (v + 63) & ~63; };
+  int sum = 0, live = 0;
   for (int q = 0; q < per; ++q) {
     const int t = beg + q;
-    if (t < n) sum += rd.tile_count[t];
+    if (t < n) {
+      const int cnt = rd.tile_count[t];
+      sum += pad64(cnt);
+      live += cnt;
+    }
   }
   // inclusive scan of the per-thread sums: wavefront shuffles, then waves
   int v = sum;
@@ -307,6 +357,10 @@ __global__ __launch_bounds__(1024) void k_scan(const BatchTable* __restrict__ bt
     if (lane >= d) v += o;
   }
   if (lane == 63) wsum[wave] = v;
+  int lv = live;
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) lv += __shfl_xor(lv, d);
+  if (lane == 0) lsum[wave] = lv;
   __syncthreads();
   if (threadIdx.x == 0) {
     int acc = 0;
@@ -319,19 +373,25 @@ __global__ __launch_bounds__(1024) void k_scan(const BatchTable* __restrict__ bt
   }
   __syncthreads();
   int run = wsum[wave] + v - sum;  // exclusive prefix of this thread's segment
+  PIC_G int* dcell = rd.cell[c->pbuf ^ 1];
   for (int q = 0; q < per; ++q) {
     const int t = beg + q;
     if (t < n) {
-      const int cnt = rd.tile_count[t];
+      const int cnt = rd.tile_count[t], full = rd.tile_full[t];
       rd.tile_start[t] = run;
-      rd.tile_cursor[t] = run;
+      rd.tile_full[t] = run;            // whole groups from the front
+      rd.tile_cursor[t] = run + full;   // then the other particles
       rd.tile_count[t] = 0;
-      run += cnt;
+      for (int e = run + cnt; e < run + pad64(cnt); ++e) dcell[e] = -1;  // padding: removed
+      run += pad64(cnt);
     }
   }
   if (threadIdx.x == 0) {
+    int lt = 0;
+    for (int q = 0; q < 16; ++q) lt += lsum[q];
     rd.tile_start[n] = carry_s;
-    c->n_live = carry_s;
+    c->n_live = lt;
+    c->n_padded = carry_s;
   }
 }
 
@@ -372,8 +432,16 @@ __global__ __launch_bounds__(256) void k_scatter(const BatchTable* __restrict__ 
         v[5] = fptr<R>(rd.u[src][2])[q];
         id = rd.pid[src][q];
       }
-      const int key = act ? tile_of<DIM, R>(rd, cc) : 0;
-      const int slot = wave_agg_add(rd.tile_cursor, key, act);
+      bool whole;
+      const int key = sort_key<DIM, R>(rd, cc, act, whole);
+      int slot;
+      if (whole) {
+        int b = 0;
+        if ((threadIdx.x & 63) == 0) b = g_add(rd.tile_full + key, 64);
+        slot = __shfl(b, 0) + (int)(threadIdx.x & 63);
+      } else {
+        slot = wave_agg_add(rd.tile_cursor, key, act);
+      }
       if (act) {
         rd.cell[dst][slot] = cc;
         fptr<R>(rd.off[dst][0])[slot] = v[0];
@@ -388,6 +456,19 @@ __global__ __launch_bounds__(256) void k_scatter(const BatchTable* __restrict__ 
   }
 }
 
+// The scan turned the whole-group counts into the front cursors the scatter
+// used: zero them for the next sort's count (a flat range over the tiles of
+// the runs that sort).
+__global__ __launch_bounds__(256) void k_full_reset(const BatchTable* __restrict__ bt) {
+  __shared__ SortItems si;
+  const long long items = sort_items(bt, bt->pre_tiles, si);
+  if (items == 0) return;
+  for (long long w = (long long)blockIdx.x * 256 + threadIdx.x; w < items; w += (long long)gridDim.x * 256) {
+    const int r = sort_item_run(si, bt->n, w);
+    bt->run[r]->tile_full[w - si.pre[r]] = 0;
+  }
+}
+
 // ------------------------------------------------------------------ commit
 __global__ void k_commit(const BatchTable* __restrict__ bt) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
@@ -399,7 +480,7 @@ __global__ void k_commit(const BatchTable* __restrict__ bt) {
   pending(rd, *c, kend, nnew);
   if (c->n_slots + nnew > rd.capacity) c->err |= 2u;
   if (kend > c->next_col) c->next_col = kend;
-  c->n_slots = c->n_live;
+  c->n_slots = c->n_padded;
   c->pbuf ^= 1;
   c->fresh = 1;
   c->last_sort = c->step;
@@ -412,6 +493,7 @@ static void chain(const BatchTable* bt, int nruns, int grid, hipStream_t s) {
   hipLaunchKernelGGL((k_count<DIM, R>), dim3(grid), dim3(256), 0, s, bt);
   hipLaunchKernelGGL(k_scan, dim3(nruns), dim3(1024), 0, s, bt);
   hipLaunchKernelGGL((k_scatter<DIM, R>), dim3(grid), dim3(256), 0, s, bt);
+  hipLaunchKernelGGL(k_full_reset, dim3(grid), dim3(256), 0, s, bt);
   hipLaunchKernelGGL(k_commit, dim3((nruns + 63) / 64), dim3(64), 0, s, bt);
 }
 

@@ -467,7 +467,9 @@ __device__ __forceinline__ void tile_geo(const BatchTable* __restrict__ bt, long
   g.p0 = (unsigned)ts[g.tile];
   g.p1 = (unsigned)ts[g.tile + 1];
   const PIC_C Counters& ctr = *ro(rd.ctr);
-  int hi[3] = {T::TZ - 1, T::TX - 1, T::TY - 1};
+  // right after a sort: the tile's cells, and GZ cells above in z, where the
+  // upper members of a group sorted by its lowest cell may sit
+  int hi[3] = {T::TZ - 1 + T::GZ, T::TX - 1, T::TY - 1};
   g.lo[0] = g.lo[1] = g.lo[2] = 0;
   if (!ctr.fresh) {
     const PIC_C int* bbr = ro(rd.bbox[ctr.bbuf]) + 6 * g.tile;

@@ -72,7 +72,7 @@ struct Layout {
   size_t rundev, ctr, tab1, tabB;
   size_t E[2][3], B[2][3], J[2][3];
   size_t cell[2], off[2][3], u[2][3], pid[2];
-  size_t tile_start, tile_count, tile_cursor, bbox[2];
+  size_t tile_start, tile_count, tile_cursor, tile_full, bbox[2];
   size_t rho_a, rho_b, gauss0, jlast[3], cell_snap, slowq;
   size_t jf[2][3];  // filtered current (R), ping-pong; only with the filter
   size_t ftmp[2];   // node scalar ping-pong of the filtered Gauss diagnostic (double)
@@ -161,6 +161,8 @@ pic_status derive(const pic_lab_params* p, Derived& d) {
     d.capacity = (long long)p->nz * d.nperp * p->ppc + 64;
     d.max_new = (long long)p->nz * d.nperp * p->ppc;
   }
+  // every tile's slot range is padded to a multiple of 64 (one wavefront)
+  d.capacity += 64LL * d.ntiles;
   if (d.capacity >= (1LL << 31) - 1) return fail(PIC_EINVAL, "too many particles for one run");
   {
     // One particle's current contribution is at most cmax = w / (dA dt) (plus
@@ -218,6 +220,7 @@ void layout(const pic_lab_params* p, const Derived& d, Layout& L) {
   L.tile_start = take(sizeof(int) * (d.ntiles + 1));
   L.tile_count = take(sizeof(int) * d.ntiles);
   L.tile_cursor = take(sizeof(int) * d.ntiles);
+  L.tile_full = take(sizeof(int) * d.ntiles);
   L.bbox[0] = take(sizeof(int) * 6 * d.ntiles);
   L.bbox[1] = take(sizeof(int) * 6 * d.ntiles);
   const bool stn = p->n_stations > 0;
@@ -587,6 +590,7 @@ pic_status pic_init_boosted(const pic_lab_params* p, void* dev_buf, size_t bytes
   h.tile_start = at<int>(r, L.tile_start);
   h.tile_count = at<int>(r, L.tile_count);
   h.tile_cursor = at<int>(r, L.tile_cursor);
+  h.tile_full = at<int>(r, L.tile_full);
   h.rho_a = at<double>(r, L.rho_a);
   h.rho_b = at<double>(r, L.rho_b);
   h.gauss0 = at<double>(r, L.gauss0);

@@ -41,24 +41,28 @@ constexpr unsigned DEAD = 0x80000000u;
 // Tile geometry (cells) and the largest LDS window a tile may use.  The
 // window spans the tile's particle bounding box widened by one cell below
 // and two above (gather and deposit stencils): W = extent + 3, so a tile's
-// particles may spread over TZ + 2 cells in z and TX + 2, TY + 2 across.
-// The z extent W_z = 13 is odd: the LDS word offsets of the cells of an
-// 8x8 transverse plane (x stride 13, y stride 169) then fall in distinct
-// banks, where with 14 they all are even (two lanes per bank).
-// 3D split precision: 8x8x8 cells, a 13x13x13 window (y stride padded to
+// particles may spread over TZ + 4 cells in z and TX + 2, TY + 2 across
+// (the sort places some up to GZ cells above the tile's z range).
+// The z extent W_z = 15 is odd, so the x offsets 15 i of a wavefront's 8x8
+// transverse plane cover every residue mod 8, and the y stride is padded
+// (below) to complete a bank-distinct pattern.
+// 3D split precision: 8x8x8 cells, a 15x13x13 window (y stride padded to
 // 200 cells) of 122 KiB (one 1024-thread workgroup per CU); 3D FP64: 8x8x4
-// cells, 13x13x9, 107 KiB.
+// cells, 15x13x9, 123 KiB.
 template <int DIM, typename R> struct Tile;
 template <typename R> struct Tile<3, R> {
   static constexpr int LZ = 3, LX = 3, LY = sizeof(R) == 4 ? 3 : 2;
   static constexpr int TZ = 1 << LZ, TX = 1 << LX, TY = 1 << LY;
-  static constexpr int WZ = TZ + 5, WX = TX + 5, WY = TY + 5;
+  static constexpr int WZ = TZ + 7, WX = TX + 5, WY = TY + 5;
   // LDS stride of y.  In split precision it is padded from WZ WX to the next
   // value = 8 (mod 64): with the odd x stride WZ, the word offsets
   // WZ i + SY j of an 8x8 transverse plane (the cells of one wavefront's
   // lanes) are then 64 distinct banks, so a pair read (z, z+1) or a 64-bit
   // atomic loads every bank exactly twice (unpadded: up to four times).
   static constexpr int SY = sizeof(R) == 4 ? WZ * WX + ((8 - WZ * WX) % 64 + 64) % 64 : WZ * WX;
+  // z cells above the tile a group sorted by its lowest cell may reach
+  // (the window still spans the tile plus this and the stencil)
+  static constexpr int GZ = sizeof(R) == 4 ? 1 : 2;
 };
 // 2D: 16x16 cells, a 22x37 window (39 KiB; four 256-thread workgroups per
 // CU): 21 cells of transverse slack, because electrons quivering in a
@@ -71,6 +75,7 @@ template <typename R> struct Tile<2, R> {
   static constexpr int TZ = 1 << LZ, TX = 1 << LX, TY = 1;
   static constexpr int WZ = TZ + 6, WX = TX + 21, WY = 1;
   static constexpr int SY = 0;  // no y
+  static constexpr int GZ = 1;  // 2D groups interleave four columns: rarely whole
 };
 
 // Yee staggering per component (half-cell flags in z, x, y):
@@ -85,6 +90,7 @@ struct Counters {
   long long step;      // index n of the next step
   long long n_slots;   // particle slots in the current buffer (live + removed + tail)
   long long n_live;    // live particles after the last sort
+  long long n_padded;  // slots after the last sort (tiles padded to 64 slots)
   long long next_col;  // next plasma lattice column to create
   long long last_sort; // step of the last sort (-1: none)
   long long n_new;     // particles created by the pending injection
@@ -133,8 +139,10 @@ struct RunDev {
   PIC_G void* u[2][3];
   PIC_G unsigned* pid[2];
   PIC_G int* tile_start;  // ntiles + 1
-  PIC_G int* tile_count;  // ntiles
-  PIC_G int* tile_cursor; // ntiles
+  PIC_G int* tile_count;  // ntiles: particles per tile (counting), then zeroed
+  PIC_G int* tile_cursor; // ntiles: next slot for particles that come in fragments
+  PIC_G int* tile_full;   // ntiles: particles that come in whole wavefronts (counting),
+                          // then the next slot for them
   PIC_G int* bbox[2];     // 6 ints per tile: lo z,x,y then hi z,x,y (tile-relative)
   PIC_G double* rho_a;
   PIC_G double* rho_b;
