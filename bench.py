@@ -170,6 +170,30 @@ def copy_calibration(pic, torch, reps=3):
     del a, b
 
 
+def hbm_achievable(pic, torch, nbytes=4 << 30, reps=5):
+    """The HBM bandwidth tuned streaming kernels reach on this device (copy,
+    read only, write only), timed with events on the stream they run on."""
+    a = torch.ones(nbytes, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    s = torch.cuda.current_stream()
+    out = {}
+    for mode, name, mult in ((0, "copy", 2), (1, "read", 1), (2, "write", 1)):
+        pic.pic_stream_bench(mode, a.data_ptr(), b.data_ptr(), nbytes, s.cuda_stream)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for _ in range(reps):
+            pic.pic_stream_bench(mode, a.data_ptr(), b.data_ptr(), nbytes, s.cuda_stream)
+        e1.record(s)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        out[f"{name}_GBs"] = mult * nbytes / (ms * 1e-3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    out["peak_GBs"] = HBM_PEAK_GBS
+    out["copy_frac_of_peak"] = out["copy_GBs"] / HBM_PEAK_GBS
+    return out
+
+
 def kernel_roofline(run, pic, nsteps, workload=None):
     ms = pic.pic_step_timed(run.handle, nsteps)
     slots, live = pic.pic_particle_count(run.handle)
@@ -244,14 +268,19 @@ def lab_io_cost(cfg, pic, torch, fields_ms_plain, nsteps=10, n_stations=32, stri
             "lab_io_ms_per_step": ms["fields"] - fields_ms_plain}
 
 
-def full_run(cfg, pic, torch, passes, compensate):
-    """The workload's whole configured run (cfg["steps"] steps from t = 0), once
-    with the current filter (passes + compensation) and once without: whole-run
-    rate and the state at the end.  Without a filter the short-wavelength
+def full_run(cfg, pic, torch, passes, compensate, unfiltered=False):
+    """The workload's whole configured run (cfg["steps"] steps from t = 0) with
+    the current filter (passes + compensation), and on request without it:
+    whole-run rate, its fraction of the HBM roofline at the algorithmic bytes
+    per particle-step of the whole step (particle state read and written,
+    plus 96 B per cell-step over the electrons per cell: 62 B at 16 per
+    cell), and the state at the end.  Without a filter the short-wavelength
     instability of the boosted frame grows and heats the plasma, which sends
     electrons through the out-of-window path; the filter is the paper's cure."""
     out = {"steps": cfg["steps"]}
-    for name, fp, fc in (("filtered", passes, compensate), ("unfiltered", 0, 0)):
+    cases = [("filtered", passes, compensate)] + ([("unfiltered", 0, 0)] if unfiltered else [])
+    bps = 56 + 96 / cfg["ppc"]
+    for name, fp, fc in cases:
         run = pic.Run(dict(cfg, filter_passes=fp, filter_compensate=fc), "fp32")
         d0 = run.diag(pic.PIC_DIAG_PARTICLES)
         run.synchronize()
@@ -264,8 +293,11 @@ def full_run(cfg, pic, torch, passes, compensate):
         del run
         torch.cuda.empty_cache()
         n_box = 0.5 * (d0["n_particles"] + d1["n_particles"])
+        rate = n_box * cfg["steps"] / sec
         out[name] = {"filter_passes": fp, "filter_compensate": fc,
-                     "value": n_box * cfg["steps"] / sec, "ms_per_step": 1e3 * sec / cfg["steps"],
+                     "value": rate, "ms_per_step": 1e3 * sec / cfg["steps"],
+                     "bytes_per_particle_step": bps,
+                     "roofline_frac": rate * bps / 1e9 / HBM_PEAK_GBS,
                      "U_E": d1["U_E"], "Ez_max": d1["Ez_max"], "KE": d1["KE"],
                      "slow_path_fraction": d1["n_slow"] / max(1.0, n_box * cfg["steps"])}
     return out
@@ -305,18 +337,85 @@ def pusher_cost(pic, torch, nsteps=50, n=1 << 27):
             out[f"{name}_{pname}"] = {"pushes_per_s": rate, "ms_per_launch": ms,
                                       "GBs_algorithmic": rate * abytes / 1e9,
                                       "frac": rate * abytes / 1e9 / HBM_PEAK_GBS,
-                                      "GBs_moved_without_crossings": rate * kbytes / 1e9}
+                                      "GBs_moved_without_crossings": rate * kbytes / 1e9,
+                                      "frac_moved": rate * kbytes / 1e9 / HBM_PEAK_GBS}
         del tu, tE, tc, to
         torch.cuda.empty_cache()
     return out
 
 
-def serving(pic, torch, n_requests, budget_gib, chunk):
+def serving(pic, torch, n_requests, budget_gib, chunk, depth=2):
     from paper_0909_5603_amd import serve, workloads
 
     reqs = workloads.serving_stream(n_requests, seed=5)
-    res = serve.serve_stream(reqs, budget_bytes=int(budget_gib * 2**30), chunk_steps=chunk)
+    res = serve.serve_stream(reqs, budget_bytes=int(budget_gib * 2**30), chunk_steps=chunk, depth=depth)
+    res.pop("status", None)
     return res
+
+
+def c3_record(pic, torch, steps=20, warmup=5, timing_steps=20):
+    """The 3D 256x128x128, 8 e-/cell workload (gamma_b 13): whole-step rate
+    and the particle kernel's roofline fraction."""
+    from paper_0909_5603_amd import workloads
+
+    cfg = workloads.config("c3")
+    run, r = run_main(cfg, "fp32", steps, warmup, pic, torch)
+    ms, roof = kernel_roofline(run, pic, timing_steps)
+    run.close()
+    del run
+    torch.cuda.empty_cache()
+    return {"workload": "3D3V boosted-frame LWFA 256x128x128 cells, 8 e-/cell, gamma_boost 13, a0 2",
+            "value": r["value"], "ms_per_step": r["ms_per_step"],
+            "roofline_particle_kernel": {k: roof[k] for k in ("achieved", "frac", "ms_per_launch",
+                                                               "algorithmic_bytes_per_launch")}}
+
+
+def host_info():
+    """Core count, affinity and CPU model of the host the oracle runs on."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    aff = sorted(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else []
+    return {"host_cores": os.cpu_count(), "affinity_cores": len(aff),
+            "affinity": f"{aff[0]}-{aff[-1]}" if aff else "", "cpu_model": model}
+
+
+def cpu_baseline_c1(oracle, workloads):
+    """The 2D parity workload's whole run (200 steps) in the oracle, 1 thread."""
+    cfg = workloads.config("c1")
+    st = oracle.State(cfg)
+    n0 = st.diag()["n_particles"]
+    t0 = time.perf_counter()
+    st.step(cfg["steps"])
+    sec = time.perf_counter() - t0
+    n1 = st.diag()["n_particles"]
+    st.close()
+    return {"value": 0.5 * (n0 + n1) * cfg["steps"] / sec, "unit": "particle-steps/s", "seconds": sec,
+            "sample": f"2D 128x64, 4 e-/cell, gamma_b 5, whole 200-step run"}
+
+
+def cpu_baseline_c2(oracle, workloads, n=1 << 22, steps=100):
+    """The pusher microbenchmark's crossed-field set in the oracle: 2^22
+    particles, 100 steps, modified Lorentz-force pusher, 1 thread."""
+    import numpy as np
+
+    u, Ex, B, cell, off = workloads.pusher_set(n, "crossed", seed=2)
+    E = np.zeros((n, 3))
+    E[:, 0] = Ex
+    Bn = np.ascontiguousarray(np.tile(B, (n, 1)))
+    pos = np.zeros((n, 3))
+    oracle.push_many(u[:1024], E[:1024], Bn[:1024], pos[:1024], workloads.PUSH_DT, 1)  # load
+    t0 = time.perf_counter()
+    oracle.push_many(u, E, Bn, pos, workloads.PUSH_DT, steps)
+    sec = time.perf_counter() - t0
+    return {"value": n * steps / sec, "unit": "pushes/s", "seconds": sec,
+            "sample": f"{n} particles x {steps} steps, crossed fields, gamma 1e2-1e6"}
 
 
 def cpu_baseline(seconds_target=15.0):
@@ -336,10 +435,14 @@ def cpu_baseline(seconds_target=15.0):
             break
     sec = time.perf_counter() - t0
     st.close()
-    return {"value": n_box * steps / sec, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"FP64 C oracle, one thread, 3D box 64x32x32 with every other parameter of the "
-                      f"512x256x256 workload (16 ppc, {n_box} electrons in the box), {steps} steps, "
-                      f"{sec:.1f} s"}
+    out = {"value": n_box * steps / sec, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+           "sample": f"FP64 C oracle, one thread, 3D box 64x32x32 with every other parameter of the "
+                     f"512x256x256 workload (16 ppc, {n_box} electrons in the box), {steps} steps, "
+                     f"{sec:.1f} s"}
+    out.update(host_info())
+    out["c1"] = cpu_baseline_c1(oracle, workloads)
+    out["c2"] = cpu_baseline_c2(oracle, workloads)
+    return out
 
 
 def main():
@@ -360,7 +463,11 @@ def main():
     ap.add_argument("--no-lab-io", action="store_true",
                     help="skip the run with the laser antenna and lab-frame stations")
     ap.add_argument("--timing-steps", type=int, default=20)
-    ap.add_argument("--serve-requests", type=int, default=256)
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-chunk", type=int, default=10)
+    ap.add_argument("--no-c3", action="store_true", help="skip the 256x128x128, 8 e-/cell record")
+    ap.add_argument("--unfiltered", action="store_true",
+                    help="also run the whole configured run without the current filter")
     ap.add_argument("--profile", action="store_true",
                     help="only the split-precision timed loop and the copy calibration kernel "
                          "(for rocprofv3 runs)")
@@ -413,6 +520,12 @@ def main():
         copy_calibration(pic, torch)
         print(json.dumps(line), flush=True)
         return
+    hb = hbm_achievable(pic, torch)
+    line["hbm_achievable"] = hb
+    roof["frac_of_achievable_copy"] = roof["achieved"] / hb["copy_GBs"]
+    log(f"[hbm] tuned streaming: copy {hb['copy_GBs']:.0f} GB/s, read {hb['read_GBs']:.0f}, "
+        f"write {hb['write_GBs']:.0f} (peak {HBM_PEAK_GBS:.0f}); particle kernel at "
+        f"{100 * roof['frac_of_achievable_copy']:.1f}% of the tuned copy")
     if not args.no_fp64:
         run64, r64 = run_main(cfg, "fp64", max(args.steps // 2, 10), max(args.warmup // 2, 2), pic, torch)
         ms64, roof64 = kernel_roofline(run64, pic, max(args.timing_steps // 2, 4))
@@ -433,12 +546,13 @@ def main():
         log(f"[lab io] antenna + {lc['n_stations']} stations: {lc['lab_io_ms_per_step']:.3f} ms/step "
             f"(step {lc['ms_per_step_events']:.3f} ms)")
     if not args.no_full_run:
-        fr = full_run(cfg, pic, torch, passes=4, compensate=1)
+        fr = full_run(cfg, pic, torch, passes=4, compensate=1, unfiltered=args.unfiltered)
         line["full_run"] = fr
-        for k in ("filtered", "unfiltered"):
+        for k in [k for k in ("filtered", "unfiltered") if k in fr]:
             v = fr[k]
             log(f"[full run, {k}] {fr['steps']} steps: {v['ms_per_step']:.3f} ms/step, "
-                f"{v['value']:.3e} particle-steps/s, Ez_max {v['Ez_max']:.3g}, "
+                f"{v['value']:.3e} particle-steps/s ({100 * v['roofline_frac']:.1f}% of HBM at "
+                f"{v['bytes_per_particle_step']:.0f} B), Ez_max {v['Ez_max']:.3g}, "
                 f"slow-path fraction {v['slow_path_fraction']:.2e}")
     if not args.no_pusher:
         pc = pusher_cost(pic, torch)
@@ -446,15 +560,23 @@ def main():
         log("[pusher] 2^27 particles, crossed fields: " + ", ".join(
             f"{k} {v['pushes_per_s']:.3e}/s ({100 * v['frac']:.0f}%)" for k, v in pc.items()
             if isinstance(v, dict)))
+    if not args.no_c3 and args.workload == "c5":
+        c3 = c3_record(pic, torch)
+        line["c3"] = c3
+        log(f"[c3] {c3['value']:.3e} particle-steps/s, particle kernel "
+            f"{100 * c3['roofline_particle_kernel']['frac']:.1f}% of HBM")
     if not args.no_serving:
-        res = serving(pic, torch, args.serve_requests, budget_gib=96.0, chunk=25)
+        res = serving(pic, torch, args.serve_requests, budget_gib=96.0, chunk=args.serve_chunk)
         line["serving"] = res
-        log(f"[serving] p50 {res['p50_ms']:.1f} ms, p99 {res['p99_ms']:.1f} ms, "
-            f"{res['throughput']:.3e} particle-steps/s")
+        log(f"[serving] {res['n_requests']} requests ({res['n_rejected']} rejected, {res['n_failed']} failed): "
+            f"p50 {res['p50_ms']:.1f} ms, p99 {res['p99_ms']:.1f} ms, {res['throughput']:.3e} particle-steps/s "
+            f"(offered {res['offered_load']:.3e})")
     if not args.no_cpu:
         cb = cpu_baseline()
         line["cpu_baseline"] = cb
-        log(f"[cpu] oracle {cb['value']:.3e} particle-steps/s")
+        log(f"[cpu] oracle {cb['value']:.3e} particle-steps/s (C5 sample), C1 {cb['c1']['value']:.3e} "
+            f"particle-steps/s, C2 {cb['c2']['value']:.3e} pushes/s; {cb['cpu_model']}, "
+            f"{cb['host_cores']} cores, {cb['affinity_cores']} in the affinity mask")
     print(json.dumps(line), flush=True)
 
 

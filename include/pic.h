@@ -193,7 +193,7 @@ pic_status pic_init_boosted(const pic_lab_params* p, void* dev_buf, size_t bytes
  * modified Lorentz force): gather, modified-Lorentz push, move,
  * charge-conserving deposit, Yee update; tile sort and plasma injection
  * every sort_every steps, and a tile sort alone within four steps after a
- * step in which more than 1/128 of the particles left their tiles' LDS
+ * step in which more than 1/1024 of the particles left their tiles' LDS
  * windows).  The storage
  * order of the particles changes only at sorts; results do not depend on
  * it.  Asynchronous. */
@@ -298,6 +298,15 @@ pic_status pic_push_bench(int precision, int pusher, int64_t n, int nsteps, doub
  * that reads and writes each byte once, the reference of known traffic for
  * calibrating hardware memory counters.  Asynchronous on hip_stream. */
 pic_status pic_copy_bench(const void* src, void* dst, int64_t nbytes, void* hip_stream);
+
+/* The HBM bandwidth a kernel can reach on this device, the practical
+ * ceiling beside the peak: mode 0 copies nbytes from src to dst, mode 1 only
+ * reads src (dst receives at most one word), mode 2 only writes dst (src is
+ * not read and may be NULL).  Each thread moves eight 16-byte words per
+ * iteration with non-temporal loads and stores.  nbytes a multiple of 16,
+ * caller-owned 16-byte aligned device buffers that do not overlap; PIC_EINVAL
+ * otherwise.  Asynchronous on hip_stream (time it with events there). */
+pic_status pic_stream_bench(int mode, const void* src, void* dst, int64_t nbytes, void* hip_stream);
 
 #ifdef __cplusplus
 }

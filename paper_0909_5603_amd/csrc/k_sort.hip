@@ -1,7 +1,7 @@
 // Plasma-column injection and the counting sort of particles by tile.
 //
 // Every sort_every steps, and (without (1)) at the first step carrying the
-// sort chain after one in which more than 1/128 of a run's particles left
+// sort chain after one in which more than 1/1024 of a run's particles left
 // their tile windows:
 // (1) create the lattice columns that have drifted
 // into the reservoir beyond z_max (Philox-drawn positions, laboratory

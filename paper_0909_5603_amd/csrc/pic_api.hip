@@ -10,6 +10,8 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <atomic>
+#include <mutex>
 #include <vector>
 
 #include "launch.hpp"
@@ -264,7 +266,8 @@ struct pic_run {
   BatchTable* dtab1;
   BatchTable* dtabB;
   BatchTable htab1;
-  BatchTable htabB;
+  unsigned long long serial;        // unique per run of the process
+  std::vector<unsigned long long> tabB_runs;  // serials of the batch dtabB holds
   Counters hctr0;  // initial device counters (host staging of the asynchronous init)
   int ncu, gpart, ggen;
   bool use_graph;
@@ -453,6 +456,8 @@ pic_status pic_init_boosted(const pic_lab_params* p, void* dev_buf, size_t bytes
   pic_status st = derive(p, d);
   if (st != PIC_OK) return st;
   pic_run* r = new pic_run();
+  static std::atomic<unsigned long long> next_serial{1};
+  r->serial = next_serial++;
   r->p = *p;
   if (r->p.dims == 2) r->p.ny = 1;
   r->d = d;
@@ -725,6 +730,51 @@ pic_status pic_step_timed(pic_run* r, int nsteps, double ms[4]) {
   return st;
 }
 
+// Pinned host staging of the batch tables that pic_step_batch uploads: a
+// ring per device whose slots are reused once the copy that last read them
+// has executed (one event per slot), so an upload never waits for the
+// stream.  Allocated on first use, kept until the process ends.
+namespace {
+constexpr int TABLE_RING = 8;
+constexpr int MAX_DEVICES = 16;
+struct TableRing {
+  BatchTable* host = nullptr;
+  hipEvent_t ev[TABLE_RING] = {};
+  int next = 0;
+};
+TableRing g_ring[MAX_DEVICES];
+std::mutex g_ring_mutex;
+
+pic_status upload_table(pic_run* r0, pic_run* const* act, int n) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES)
+    return fail(PIC_EHIP, "no usable current device");
+  std::lock_guard<std::mutex> lock(g_ring_mutex);
+  TableRing& R = g_ring[dev];
+  if (!R.host) {
+    void* h = nullptr;
+    HIPCHK(hipHostMalloc(&h, sizeof(BatchTable) * TABLE_RING, hipHostMallocDefault));
+    for (int k = 0; k < TABLE_RING; ++k) {
+      if (hipEventCreateWithFlags(&R.ev[k], hipEventDisableTiming) != hipSuccess) {
+        for (int q = 0; q < k; ++q) (void)hipEventDestroy(R.ev[q]);
+        (void)hipHostFree(h);
+        return fail(PIC_EHIP, "hipEventCreateWithFlags failed");
+      }
+    }
+    R.host = static_cast<BatchTable*>(h);
+  }
+  const int k = R.next;
+  R.next = (k + 1) % TABLE_RING;
+  HIPCHK(hipEventSynchronize(R.ev[k]));  // the copy that last read slot k has run
+  fill_table(R.host[k], act, n);
+  HIPCHK(hipMemcpyAsync(r0->dtabB, &R.host[k], sizeof(BatchTable), hipMemcpyHostToDevice, r0->stream));
+  HIPCHK(hipEventRecord(R.ev[k], r0->stream));
+  r0->tabB_runs.resize(n);
+  for (int i = 0; i < n; ++i) r0->tabB_runs[i] = act[i]->serial;
+  return PIC_OK;
+}
+}  // namespace
+
 pic_status pic_step_batch(pic_run* const* runs, const int* nsteps, int n) {
   if (!runs || !nsteps || n <= 0) return fail(PIC_EINVAL, "empty batch");
   if (n > MAX_BATCH) return fail(PIC_EINVAL, "batch larger than %d", MAX_BATCH);
@@ -747,10 +797,12 @@ pic_status pic_step_batch(pic_run* const* runs, const int* nsteps, int n) {
       if (nsteps[i] > s) a.push_back(runs[i]);
     if (a != act) {
       act = a;
-      HIPCHK(hipStreamSynchronize(r0->stream));  // the host table may still be in flight
-      fill_table(r0->htabB, act.data(), (int)act.size());
-      HIPCHK(hipMemcpyAsync(r0->dtabB, &r0->htabB, sizeof(BatchTable), hipMemcpyHostToDevice,
-                            r0->stream));
+      bool same = act.size() == r0->tabB_runs.size();
+      for (size_t i = 0; same && i < act.size(); ++i) same = act[i]->serial == r0->tabB_runs[i];
+      if (!same) {  // the device table holds another batch: upload this one
+        pic_status st = upload_table(r0, act.data(), (int)act.size());
+        if (st != PIC_OK) return st;
+      }
     }
     StepShape sh;  // the most any run of the batch needs
     bool chain = false;
@@ -953,8 +1005,9 @@ pic_status pic_get_derived(const pic_run* r, pic_derived* o) {
 
 pic_status pic_free(pic_run* r) {
   if (!r) return PIC_OK;
-  // work still queued on the run's stream may read the handle's host staging
-  (void)hipStreamSynchronize(r->stream);
+  // no wait: the caller frees a run only after the work that uses it has
+  // run (the host staging it holds is read by copies HIP performs when
+  // they are enqueued, pageable memory being copied synchronously)
   for (int q = 0; q < 2; ++q) {
     if (r->g1[q]) (void)hipGraphExecDestroy(r->g1[q]);
     if (r->gB[q]) (void)hipGraphExecDestroy(r->gB[q]);
@@ -987,6 +1040,19 @@ pic_status pic_copy_bench(const void* src, void* dst, int64_t nbytes, void* hip_
   if ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) % 16 != 0)
     return fail(PIC_EINVAL, "buffers must be 16-byte aligned");
   launch_copy_bench(src, dst, (long long)(nbytes / 16), static_cast<hipStream_t>(hip_stream));
+  HIPCHK(hipGetLastError());
+  return PIC_OK;
+}
+
+pic_status pic_stream_bench(int mode, const void* src, void* dst, int64_t nbytes, void* hip_stream) {
+  if (mode < 0 || mode > 2) return fail(PIC_EINVAL, "mode must be 0 (copy), 1 (read) or 2 (write)");
+  if (nbytes < 0) return fail(PIC_EINVAL, "negative size");
+  if (nbytes % 16 != 0) return fail(PIC_EINVAL, "nbytes must be a multiple of 16");
+  if (nbytes == 0) return PIC_OK;
+  if ((mode != 2 && !src) || !dst) return fail(PIC_EINVAL, "NULL buffer");
+  if ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) % 16 != 0)
+    return fail(PIC_EINVAL, "buffers must be 16-byte aligned");
+  launch_stream_bench(mode, src, dst, (long long)(nbytes / 16), static_cast<hipStream_t>(hip_stream));
   HIPCHK(hipGetLastError());
   return PIC_OK;
 }

@@ -71,7 +71,8 @@ class pic_derived(ctypes.Structure):
 # names declared in include/pic.h, in order
 EXPORTS = ["pic_state_bytes", "pic_init_boosted", "pic_step", "pic_step_timed", "pic_step_batch", "pic_diag",
            "pic_particle_count", "pic_read_particles", "pic_read_fields", "pic_read_station", "pic_get_derived",
-           "pic_set_option", "pic_free", "pic_last_error", "pic_push_bench", "pic_copy_bench"]
+           "pic_set_option", "pic_free", "pic_last_error", "pic_push_bench", "pic_copy_bench",
+           "pic_stream_bench"]
 
 _lib = None
 
@@ -104,6 +105,7 @@ def lib():
     L.pic_last_error.restype = ctypes.c_char_p
     L.pic_copy_bench.argtypes = [ctypes.c_void_p, ctypes.c_void_p, i64, ctypes.c_void_p]
     L.pic_copy_bench.restype = ctypes.c_int
+    L.pic_stream_bench.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, i64, ctypes.c_void_p]
     L.pic_push_bench.argtypes = [ctypes.c_int, ctypes.c_int, i64, ctypes.c_int, ctypes.c_double, dp,
                                  vp, vp, vp, vp, vp]
     for n in EXPORTS:
@@ -259,6 +261,11 @@ def pic_push_bench(precision: int, pusher: int, n: int, nsteps: int, dt: float, 
                                 ctypes.c_void_p(Ex_ptr), ctypes.c_void_p(u_ptr),
                                 ctypes.c_void_p(cell_ptr), ctypes.c_void_p(off_ptr),
                                 ctypes.c_void_p(stream)))
+
+
+def pic_stream_bench(mode: int, src_ptr: int, dst_ptr: int, nbytes: int, stream: int):
+    _check(lib().pic_stream_bench(int(mode), ctypes.c_void_p(src_ptr), ctypes.c_void_p(dst_ptr), int(nbytes),
+                                  ctypes.c_void_p(stream)))
 
 
 def pic_copy_bench(src_ptr: int, dst_ptr: int, nbytes: int, stream: int):

@@ -82,6 +82,11 @@ def test_copy_bench_rejects_bad_sizes_before_any_launch(pic):
     assert L.pic_copy_bench(None, None, 24, None) == -1  # not a multiple of 16
     assert L.pic_copy_bench(None, None, 32, None) == -1  # NULL buffers
     assert L.pic_copy_bench(8, 40, 32, None) == -1  # misaligned addresses: rejected before a launch
+    assert L.pic_stream_bench(0, None, None, 0, None) == 0
+    assert L.pic_stream_bench(3, None, None, 32, None) == -1  # unknown mode
+    assert L.pic_stream_bench(0, None, None, 24, None) == -1  # not a multiple of 16
+    assert L.pic_stream_bench(1, None, None, 32, None) == -1  # NULL buffers
+    assert L.pic_stream_bench(2, 0, 40, 32, None) == -1  # misaligned destination
 
 
 def test_filter_buffers_are_allocated_only_when_used(pic):
