@@ -208,6 +208,18 @@ pic_status pic_step(pic_run* run, int nsteps);
  * done.  Asynchronous; PIC_EINVAL for an invalid batch, nothing enqueued. */
 pic_status pic_step_batch(pic_run* const* runs, const int* nsteps, int n);
 
+/* For callers that cannot allocate memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation): the same steps as
+ * pic_step_batch, with the same arguments, rules and results, but the batch
+ * table the kernels read lives in a device array of the library (one table,
+ * sizeof(BatchTable) = 10 KiB, per GPU, kept until the process ends) and the
+ * steps are launched directly, so the call allocates no device or pinned
+ * host memory and creates no graph or event.  Limit: n <= 256 runs
+ * (PIC_EINVAL beyond).  Every call on a GPU shares that GPU's table, which
+ * holds the last call's batch: calls that overlap on one GPU (on different
+ * streams) race, and must be ordered by the caller. */
+pic_status pic_step_batch_noalloc(pic_run* const* runs, const int* nsteps, int n);
+
 /* Enqueue nsteps steps without graph replay, bracketing each stage with HIP
  * events recorded on the run's stream, synchronise, and return the mean
  * device time per step of each stage in milliseconds: ms[0] = injection and

@@ -46,6 +46,8 @@ void launch_bshift(int prec, const RunDev* rd, long long npts, int src, int dst,
 // pusher microbenchmark
 void launch_copy_bench(const void* src, void* dst, long long n16, hipStream_t s);
 void launch_stream_bench(int mode, const void* src, void* dst, long long n16, hipStream_t s);
+// this device's batch table of pic_step_batch_noalloc (file-scope device array)
+hipError_t batch_scratch(BatchTable** out);
 void launch_push_bench(int prec, int pusher, long long n, double dt, const double B[3], void* Ex,
                        void* u, int* cell, void* off, hipStream_t s);
 

@@ -836,6 +836,59 @@ pic_status pic_step_batch(pic_run* const* runs, const int* nsteps, int n) {
   return PIC_OK;
 }
 
+pic_status pic_step_batch_noalloc(pic_run* const* runs, const int* nsteps, int n) {
+  if (!runs || !nsteps || n <= 0) return fail(PIC_EINVAL, "empty batch");
+  if (n > MAX_BATCH) return fail(PIC_EINVAL, "batch larger than %d", MAX_BATCH);
+  pic_run* r0 = runs[0];
+  int maxs = 0;
+  for (int i = 0; i < n; ++i) {
+    if (!runs[i]) return fail(PIC_EINVAL, "run %d is NULL", i);
+    if (runs[i]->p.dims != r0->p.dims || runs[i]->p.precision != r0->p.precision ||
+        runs[i]->p.pusher != r0->p.pusher)
+      return fail(PIC_EINVAL, "batched runs must share dims, precision and pusher");
+    if (runs[i]->p.diag_flags & PIC_DIAGF_CONTINUITY)
+      return fail(PIC_EINVAL, "continuity diagnostics are single-run only");
+    if (nsteps[i] < 0) return fail(PIC_EINVAL, "nsteps[%d] < 0", i);
+    maxs = nsteps[i] > maxs ? nsteps[i] : maxs;
+  }
+  BatchTable* tab = nullptr;  // this device's table (set up on the first call)
+  HIPCHK(batch_scratch(&tab));
+  // everything below lives on the stack: no allocation of any kind
+  BatchTable host;
+  pic_run* act[MAX_BATCH];
+  int nact = -1;
+  for (int s = 0; s < maxs; ++s) {
+    pic_run* a[MAX_BATCH];
+    int na = 0;
+    for (int i = 0; i < n; ++i)
+      if (nsteps[i] > s) a[na++] = runs[i];
+    bool same = na == nact;
+    for (int i = 0; same && i < na; ++i) same = a[i] == act[i];
+    if (!same) {
+      // the whole table is rewritten (fill_table clears it first); a copy
+      // from pageable memory is performed by HIP when it is enqueued, in
+      // stream order after the steps already enqueued on r0's stream
+      for (int i = 0; i < na; ++i) act[i] = a[i];
+      nact = na;
+      fill_table(host, act, nact);
+      HIPCHK(hipMemcpyAsync(tab, &host, sizeof(BatchTable), hipMemcpyHostToDevice, r0->stream));
+    }
+    StepShape sh;
+    bool chain = false;
+    for (int i = 0; i < nact; ++i) {
+      chain = chain || chain_step(act[i]);
+      const StepShape qs = shape_of(act[i]);
+      sh.fstages = std::max(sh.fstages, qs.fstages);
+      sh.st_items = std::max(sh.st_items, qs.st_items);
+      sh.ant_plane = std::max(sh.ant_plane, qs.ant_plane);
+    }
+    enqueue_step(r0, tab, false, chain, sh);  // direct launches: no graph is built
+    for (int i = 0; i < nact; ++i) host_advance(act[i]);
+  }
+  HIPCHK(hipGetLastError());
+  return PIC_OK;
+}
+
 pic_status pic_diag(pic_run* r, unsigned what, pic_diag_out* out) {
   if (!r || !out) return fail(PIC_EINVAL, "NULL argument");
   hipStream_t s = r->stream;

@@ -69,7 +69,8 @@ class pic_derived(ctypes.Structure):
 
 
 # names declared in include/pic.h, in order
-EXPORTS = ["pic_state_bytes", "pic_init_boosted", "pic_step", "pic_step_timed", "pic_step_batch", "pic_diag",
+EXPORTS = ["pic_state_bytes", "pic_init_boosted", "pic_step", "pic_step_timed", "pic_step_batch",
+           "pic_step_batch_noalloc", "pic_diag",
            "pic_particle_count", "pic_read_particles", "pic_read_fields", "pic_read_station", "pic_get_derived",
            "pic_set_option", "pic_free", "pic_last_error", "pic_push_bench", "pic_copy_bench",
            "pic_stream_bench"]
@@ -92,6 +93,7 @@ def lib():
     L.pic_step.argtypes = [vp, ctypes.c_int]
     L.pic_step_timed.argtypes = [vp, ctypes.c_int, dp]
     L.pic_step_batch.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_int), ctypes.c_int]
+    L.pic_step_batch_noalloc.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_int), ctypes.c_int]
     L.pic_diag.argtypes = [vp, ctypes.c_uint, ctypes.POINTER(pic_diag_out)]
     L.pic_particle_count.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
     L.pic_read_particles.argtypes = [vp, i64, i64] + [dp] * 6 + [ctypes.POINTER(ctypes.c_uint32),
@@ -181,6 +183,13 @@ def pic_step_batch(runs, nsteps):
     arr = (ctypes.c_void_p * n)(*runs)
     st = (ctypes.c_int * n)(*[int(s) for s in nsteps])
     _check(lib().pic_step_batch(arr, st, n))
+
+
+def pic_step_batch_noalloc(runs, nsteps):
+    n = len(runs)
+    arr = (ctypes.c_void_p * n)(*runs)
+    st = (ctypes.c_int * n)(*[int(s) for s in nsteps])
+    _check(lib().pic_step_batch_noalloc(arr, st, n))
 
 
 def pic_diag(run: int, what: int = PIC_DIAG_ALL) -> dict:
