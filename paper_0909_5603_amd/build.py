@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libpic.so")
 OBJ = os.path.join(HERE, "_build")
-SOURCES = ["k_step.hip", "k_sort.hip", "k_aux.hip", "k_station.hip", "k_antenna.hip", "k_push_bench.hip",
+SOURCES = ["k_step.hip", "k_filter.hip", "k_sort.hip", "k_aux.hip", "k_station.hip", "k_antenna.hip", "k_push_bench.hip",
            "k_batch_scratch.hip", "pic_api.hip"]
 # the C ABI holds host code only: no device pass (the device pass types the
 # run descriptor's pointers with the global and constant address spaces)

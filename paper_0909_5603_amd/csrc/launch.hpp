@@ -15,6 +15,8 @@ int grid_generic(int ncu);
 void launch_sort_chain(int dims, int prec, const BatchTable* bt, int nruns, int grid, hipStream_t s);
 void launch_particles(int dims, int prec, int pusher, const BatchTable* bt, int grid, hipStream_t s);
 // ant_plane: transverse points of the largest run with a laser antenna (0: none)
+// the low-pass filter of the deposited current, before the E update (k_filter.hip)
+void launch_filter(int dims, int prec, const BatchTable* bt, int grid, int filter_stages, hipStream_t s);
 void launch_fields(int dims, int prec, const BatchTable* bt, int grid, int filter_stages, long long ant_plane,
                    hipStream_t s);
 // laser antenna sources: phase 0 adds -dt M^n to B^{n+1/2}, phase 1 -dt J^{n+1/2} to E^{n+1}
