@@ -471,6 +471,9 @@ def main():
     ap.add_argument("--profile", action="store_true",
                     help="only the split-precision timed loop and the copy calibration kernel "
                          "(for rocprofv3 runs)")
+    ap.add_argument("--profile-filter", type=int, metavar="PASSES",
+                    help="only the workload with the current filter (PASSES binomial passes plus "
+                         "compensation): 5 steps, then 10 event-timed steps (for rocprofv3 runs)")
     ap.add_argument("--summarize-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the particle kernel's traffic summary from two rocprofv3 --pmc "
                          "counter_collection.csv files (FETCH_SIZE run, WRITE_SIZE run)")
@@ -494,6 +497,16 @@ def main():
         sys.exit(1)
     pic.lib()
     cfg = workloads.config(args.workload)
+    if args.profile_filter is not None:
+        fcfg = dict(cfg, filter_passes=args.profile_filter, filter_compensate=1)
+        run = pic.Run(fcfg, "fp32")
+        run.step(5)
+        run.synchronize()
+        ms = pic.pic_step_timed(run.handle, 10)
+        run.close()
+        print(json.dumps({"workload": args.workload, "filter_passes": args.profile_filter,
+                          "filter_compensate": 1, "stage_ms_per_step": ms}), flush=True)
+        return
     line = {"metric": METRIC, "unit": "particle-steps/s", "n_gpus": 1, "steps": args.steps,
             "warmup": args.warmup, "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": "f32", "data": "synthetic"}
