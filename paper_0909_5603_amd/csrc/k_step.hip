@@ -655,7 +655,13 @@ void k_particles(const BatchTable* __restrict__ bt) {
       }
     }
     if (threadIdx.x == 0) sm.next = 0;
-    if (threadIdx.x < 6) sm.bb[threadIdx.x] = threadIdx.x < 3 ? (1 << 20) : -(1 << 20);
+    {
+      // recomputed here (not hoisted out of the tile loop into a spill slot,
+      // whose reload would wait on the next window's loads in flight)
+      int t6 = (int)threadIdx.x, big = 1 << 20;
+      asm volatile("" : "+v"(t6), "+v"(big));
+      if (t6 < 6) sm.bb[t6] = t6 < 3 ? big : -big;
+    }
     __syncthreads();
     // ---- B^n = B^{n-1/2} - dt/2 curl E^n on the window (last layer unused)
     {
@@ -809,6 +815,14 @@ void k_particles(const BatchTable* __restrict__ bt) {
         }
       }
     }
+    // ---- the next tile's window loads, issued as soon as this wavefront has
+    // no particles left: in flight during the tail, the reduction and the flush
+    TileGeo<DIM> gn;
+    gn.p0 = gn.p1 = 0;
+    if (wn < xs.end) {
+      tile_geo<DIM, R>(bt, wn, gn);
+      if (gn.p0 < gn.p1) window_load<DIM, R, BLOCK, NU>(bt, gn, ld, sidx, zf);
+    }
     if (bad) g_or(&rd.ctr->err, 1u);
     // ---- bounding box of the new positions
 #pragma unroll
@@ -829,22 +843,17 @@ void k_particles(const BatchTable* __restrict__ bt) {
       atomicMax(&sm.bb[5], bmax2);
     }
     __syncthreads();
-    if (threadIdx.x < 6) {
-      const int t = threadIdx.x;
+    int t6 = (int)threadIdx.x, big = 1 << 20;
+    asm volatile("" : "+v"(t6), "+v"(big));
+    if (t6 < 6) {
+      const int t = t6;
       int v = sm.bb[t];
       // window -> tile-relative coordinates (window origin = tile origin + lo - 1)
       const int d = t < 3 ? t : t - 3;
       const int lod = d == 0 ? g.lo[0] : (d == 1 ? g.lo[1] : g.lo[2]);  // no dynamic index
-      if (v != (t < 3 ? (1 << 20) : -(1 << 20))) v += lod - 1;
+      if (v != (t < 3 ? big : -big)) v += lod - 1;
       if (DIM == 2 && (t == 2 || t == 5)) v = 0;
       bbw[t] = v;
-    }
-    // ---- the next tile's window loads, in flight during the flush below
-    TileGeo<DIM> gn;
-    gn.p0 = gn.p1 = 0;
-    if (wn < xs.end) {
-      tile_geo<DIM, R>(bt, wn, gn);
-      if (gn.p0 < gn.p1) window_load<DIM, R, BLOCK, NU>(bt, gn, ld, sidx, zf);
     }
     // ---- flush the current window to HBM and zero it for the next tile
     const Arr3<unsigned long long> Jg = PIC_ARR3(unsigned long long, rd.J[fb]);
