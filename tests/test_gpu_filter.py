@@ -49,6 +49,14 @@ CASES = {
         filter_passes=1, filter_compensate=1),
     "3d_open_n2": lambda: workloads.config(
         "c5", nz=48, nx=16, ny=16, ppc=2, gamma_boost=13.0, waist=0.3, filter_passes=2),
+    # more than five passes in 3D (the kernels' wide register halo)
+    "3d_open_n6_comp": lambda: workloads.config(
+        "c5", nz=48, nx=16, ny=16, ppc=2, gamma_boost=13.0, waist=0.3, filter_passes=6,
+        filter_compensate=1),
+    # more passes than z points: the open-end rule applied beyond a whole
+    # reflection of the column
+    "c1_nz8_n12_comp": lambda: workloads.config("c1", nz=8, filter_passes=12, filter_compensate=1),
+    "c1_nz8_periodic_n12": lambda: workloads.config("c1", nz=8, bc_z="periodic", filter_passes=12),
 }
 
 
