@@ -550,14 +550,14 @@ __device__ __forceinline__ void window_load(const BatchTable* __restrict__ bt, c
   }
 }
 
-// Occupancy of the 3D particle kernel.  Its LDS window (103 KiB in split
-// precision, 107 KiB in FP64) admits one workgroup per CU, so the workgroup
+// Occupancy of the 3D particle kernel.  Its LDS window (122 KiB in split
+// precision, 123 KiB in FP64) admits one workgroup per CU, so the workgroup
 // is 1024 threads in split precision (16 resident waves per CU, registers
 // capped at 128) and 512 in FP64 (8 waves; the FP64 state needs the
 // registers).  The larger split-precision tile (8x8x8 cells, 8192 particles
 // at 16 per cell) spreads the window load and the current flush over twice
-// the particles of an 8x8x4 tile: 11.0 against 11.9 ms per step at
-// 512x256x256.
+// the particles of an 8x8x4 tile (11.0 against 11.9 ms per step at
+// 512x256x256 when the change was made).
 #ifndef PIC_PBLOCK3
 #define PIC_PBLOCK3 1024
 #endif
