@@ -73,6 +73,15 @@ def test_null_arguments(pic):
     out = ctypes.c_void_p()
     p = pic.make_params(workloads.config("c1"))
     assert L.pic_init_boosted(ctypes.byref(p), None, 0, None, ctypes.byref(out)) == -1
+    # the batched steps reject an empty, oversized or NULL-holding batch
+    # before touching a device
+    runs = (ctypes.c_void_p * 257)()
+    steps = (ctypes.c_int * 257)(*([1] * 257))
+    for fn in (L.pic_step_batch, L.pic_step_batch_noalloc):
+        assert fn(None, None, 0) == -1
+        assert fn(runs, steps, 0) == -1
+        assert fn(runs, steps, 257) == -1
+        assert fn(runs, steps, 2) == -1  # NULL runs
 
 
 def test_copy_bench_rejects_bad_sizes_before_any_launch(pic):
