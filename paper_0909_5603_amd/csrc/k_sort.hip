@@ -333,65 +333,64 @@ __global__ __launch_bounds__(1024) void k_scan(const BatchTable* __restrict__ bt
   PIC_G Counters* c = rd.ctr;
   if (!sort_due(*c, rd.inject_every)) return;
   __shared__ int wsum[16], lsum[16];
-  __shared__ int carry_s;
   const int n = rd.ntiles;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int per = (n + 1023) / 1024;
-  const int beg = threadIdx.x * per;
   // tile t occupies pad64(count) slots
   auto pad64 = [](int v) { return (v + 63) & ~63; };
-  int sum = 0, live = 0;
-  for (int q = 0; q < per; ++q) {
-    const int t = beg + q;
-    if (t < n) {
-      const int cnt = rd.tile_count[t];
-      sum += pad64(cnt);
-      live += cnt;
+  PIC_G int* dcell = rd.cell[c->pbuf ^ 1];
+  // blocks of 1024 consecutive tiles, one per thread (coalesced); the
+  // running total (carry) is the same in every thread
+  int carry = 0, live = 0;
+  for (int base = 0; base < n; base += 1024) {
+    const int t = base + (int)threadIdx.x;
+    const int cnt = t < n ? rd.tile_count[t] : 0;
+    const int full = t < n ? rd.tile_full[t] : 0;
+    const int sz = pad64(cnt);
+    live += cnt;
+    // inclusive scan of the padded sizes: wavefront shuffles, then waves
+    int v = sz;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const int o = __shfl_up(v, d);
+      if (lane >= d) v += o;
     }
-  }
-  // inclusive scan of the per-thread sums: wavefront shuffles, then waves
-  int v = sum;
+    if (lane == 63) wsum[wave] = v;
+    __syncthreads();
+    int wpre = 0, tot = 0;
 #pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const int o = __shfl_up(v, d);
-    if (lane >= d) v += o;
-  }
-  if (lane == 63) wsum[wave] = v;
-  int lv = live;
-#pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) lv += __shfl_xor(lv, d);
-  if (lane == 0) lsum[wave] = lv;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int acc = 0;
     for (int q = 0; q < 16; ++q) {
       const int x = wsum[q];
-      wsum[q] = acc;
-      acc += x;
+      wpre += q < wave ? x : 0;
+      tot += x;
     }
-    carry_s = acc;
-  }
-  __syncthreads();
-  int run = wsum[wave] + v - sum;  // exclusive prefix of this thread's segment
-  PIC_G int* dcell = rd.cell[c->pbuf ^ 1];
-  for (int q = 0; q < per; ++q) {
-    const int t = beg + q;
+    const int start = carry + wpre + v - sz;  // exclusive prefix
     if (t < n) {
-      const int cnt = rd.tile_count[t], full = rd.tile_full[t];
-      rd.tile_start[t] = run;
-      rd.tile_full[t] = run;            // whole groups from the front
-      rd.tile_cursor[t] = run + full;   // then the other particles
+      rd.tile_start[t] = start;
+      rd.tile_full[t] = start;            // whole groups from the front
+      rd.tile_cursor[t] = start + full;   // then the other particles
       rd.tile_count[t] = 0;
-      for (int e = run + cnt; e < run + pad64(cnt); ++e) dcell[e] = -1;  // padding: removed
-      run += pad64(cnt);
     }
+    // padding, marked removed: the tail of each tile's last 64-slot block
+    // (every start is a multiple of 64), one wavefront store per tile
+    const int padn = sz - cnt, pbeg = start + cnt;
+#pragma unroll 8
+    for (int j = 0; j < 64; ++j) {
+      const int pj = __shfl(padn, j), ej = __shfl(pbeg, j);
+      if (lane < pj) dcell[ej + lane] = -1;
+    }
+    carry += tot;
+    __syncthreads();  // wsum is reused by the next block
   }
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) live += __shfl_xor(live, d);
+  if (lane == 0) lsum[wave] = live;
+  __syncthreads();
   if (threadIdx.x == 0) {
     int lt = 0;
     for (int q = 0; q < 16; ++q) lt += lsum[q];
-    rd.tile_start[n] = carry_s;
+    rd.tile_start[n] = carry;
     c->n_live = lt;
-    c->n_padded = carry_s;
+    c->n_padded = carry;
   }
 }
 
