@@ -86,20 +86,6 @@ __device__ __forceinline__ int wave_agg_add(PIC_G int* base, int key, bool activ
   return b + (int)__popcll(mine & ((1ull << lane) - 1ull));
 }
 
-// the same count without the slots: one non-returning atomic per distinct
-// key of the wavefront
-__device__ __forceinline__ void wave_agg_count(PIC_G int* base, int key, bool active) {
-  const int lane = threadIdx.x & 63;
-  unsigned long long pend = __ballot(active);
-  while (pend) {
-    const int leader = __ffsll((long long)pend) - 1;
-    const int lkey = __shfl(key, leader);
-    const unsigned long long m = __ballot(active && key == lkey);
-    if (lane == leader) (void)g_add(base + lkey, (int)__popcll(m));
-    pend &= ~m;
-  }
-}
-
 // Sort key of the particles of one source wavefront (uniform decision).
 // The wavefront is a whole group if its 64 slots are live, span at most
 // GZ + 1 consecutive z cells (two in split precision, where a group is one
@@ -290,11 +276,20 @@ __global__ __launch_bounds__(256) void k_inject(const BatchTable* __restrict__ b
 }
 
 // ------------------------------------------------------------------ count
+// Per-tile counts of a work item, gathered in a small LDS hash table first:
+// the slots of an item (consecutive, sorted by tile at the previous sort)
+// fall into a handful of tiles, so the global counters, which every item of
+// a tile would otherwise hit wavefront by wavefront, take a few atomics per
+// item.  A table that fills up (never with sorted input) counts directly.
+constexpr int COUNT_HASH = 64;
+
 template <int DIM, typename R>
 __global__ __launch_bounds__(256) void k_count(const BatchTable* __restrict__ bt) {
   __shared__ SortItems si;
+  __shared__ int hkey[COUNT_HASH], hcnt[COUNT_HASH], hfull[COUNT_HASH];
   const long long items = sort_items(bt, bt->pre_partblk, si);
   if (items == 0) return;
+  const int lane = threadIdx.x & 63;
   const XcdSplit xs(items);
   for (long long w = xs.beg; w < xs.end; w += xs.stride) {
     const int r = __builtin_amdgcn_readfirstlane(sort_item_run(si, bt->n, w));
@@ -305,24 +300,66 @@ __global__ __launch_bounds__(256) void k_count(const BatchTable* __restrict__ bt
     long long total = c.n_slots + nnew;
     if (total > rd.capacity) total = rd.capacity;
     const long long blk = w - si.pre[r];
-    if (blk * PART_CHUNK >= total) continue;
+    if (blk * PART_CHUNK >= total) continue;  // uniform over the workgroup
+    for (int e = threadIdx.x; e < COUNT_HASH; e += 256) {
+      hkey[e] = -1;
+      hcnt[e] = 0;
+      hfull[e] = 0;
+    }
+    __syncthreads();
+    // n particles go to tile key (full: as a whole group)
+    auto tally = [&](int key, int n, bool full) {
+      int h = key & (COUNT_HASH - 1);
+      for (int probe = 0; probe < COUNT_HASH; ++probe) {
+        const int prev = atomicCAS(&hkey[h], -1, key);
+        if (prev == -1 || prev == key) {
+          atomicAdd(&hcnt[h], n);
+          if (full) atomicAdd(&hfull[h], n);
+          return;
+        }
+        h = (h + 1) & (COUNT_HASH - 1);
+      }
+      (void)g_add(rd.tile_count + key, n);
+      if (full) (void)g_add(rd.tile_full + key, n);
+    };
     const PIC_G int* cellp = rd.cell[c.pbuf];
-    for (int t = threadIdx.x; t < PART_CHUNK; t += 256) {
-      const long long q = blk * PART_CHUNK + t;
-      int cc = -1;
-      if (q < total) cc = cellp[q];
+    // all the item's loads first (the key computation below waits on each)
+    constexpr int PER = PART_CHUNK / 256;
+    int cv[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const long long q = blk * PART_CHUNK + threadIdx.x + u * 256;
+      cv[u] = q < total ? cellp[q] : -1;
+    }
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int cc = cv[u];
       const bool act = cc >= 0;
       bool whole;
       const int key = sort_key<DIM, R>(rd, cc, act, whole);
       if (whole) {
-        if ((threadIdx.x & 63) == 0) {
-          (void)g_add(rd.tile_count + key, 64);
-          (void)g_add(rd.tile_full + key, 64);
-        }
+        if (lane == 0) tally(key, 64, true);
       } else {
-        wave_agg_count(rd.tile_count, key, act);
+        // one tally per distinct key of the wavefront
+        unsigned long long pend = __ballot(act);
+        while (pend) {
+          const int leader = __ffsll((long long)pend) - 1;
+          const int lkey = __shfl(key, leader);
+          const unsigned long long m = __ballot(act && key == lkey);
+          if (lane == leader) tally(lkey, (int)__popcll(m), false);
+          pend &= ~m;
+        }
       }
     }
+    __syncthreads();
+    for (int e = threadIdx.x; e < COUNT_HASH; e += 256) {
+      const int k = hkey[e];
+      if (k >= 0) {
+        if (hcnt[e]) (void)g_add(rd.tile_count + k, hcnt[e]);
+        if (hfull[e]) (void)g_add(rd.tile_full + k, hfull[e]);
+      }
+    }
+    __syncthreads();  // the table is cleared for the next item
   }
 }
 
