@@ -5,8 +5,9 @@
 // their tile windows:
 // (1) create the lattice columns that have drifted
 // into the reservoir beyond z_max (Philox-drawn positions, laboratory
-// Maxwellian momenta boosted to the frame: Sec. 2, second paragraph - the
-// plasma is denser and drifting in the boosted frame), appending them after
+// Maxwellian momenta boosted to the frame: Sec. 2, second paragraph - a
+// plasma at rest in the laboratory streams toward -z here, its density
+// raised by gamma_boost), appending them after
 // the current slots; (2) count live particles per tile; (3) exclusive scan of
 // the counts, each tile's range padded to a multiple of 64 slots with
 // removed markers (one workgroup per run); (4) scatter into the other
