@@ -16,6 +16,11 @@
  * device memory; it owns only the small host-side handle and any HIP graphs
  * it captures.  The buffer must stay alive and untouched until pic_free().
  *
+ * Device.  A run lives on the HIP device that is current when
+ * pic_init_boosted() is called; every later call on it (and every batched
+ * call, whose runs must all live there) must be made with that device
+ * current.
+ *
  * Errors.  No call throws.  Argument errors are returned synchronously as a
  * negative pic_status and described by pic_last_error() (thread-local).
  * Errors raised inside kernels (non-finite momentum, particle capacity
@@ -212,7 +217,8 @@ pic_status pic_step_batch(pic_run* const* runs, const int* nsteps, int n);
  * tight serving loops, harnesses that forbid allocation): the same steps as
  * pic_step_batch, with the same arguments, rules and results, but the batch
  * table the kernels read lives in a device array of the library (one table,
- * sizeof(BatchTable) = 10 KiB, per GPU, kept until the process ends) and the
+ * sizeof(BatchTable) = 10 KiB, per GPU, kept until the process ends; the
+ * current device's is used, and set up on the first call there) and the
  * steps are launched directly, so the call allocates no device or pinned
  * host memory and creates no graph or event.  Limit: n <= 256 runs
  * (PIC_EINVAL beyond).  Every call on a GPU shares that GPU's table, which
