@@ -61,6 +61,32 @@ def test_noalloc_batch_matches_the_batch_entry_point(precision):
         r.close()
 
 
+def test_noalloc_batch_with_filter_antenna_and_stations():
+    """Runs with the current filter, a laser antenna and lab-frame stations in
+    the batch (the launches those options add) give the same results."""
+    cfgs = [workloads.config("c1", nz=64, nx=32, ppc=2, seed=31),
+            workloads.config("c1", nz=64, nx=32, ppc=2, seed=32, filter_passes=2, filter_compensate=1),
+            workloads.config("c1", seed=33, filter_passes=1, n_stations=3, station_z0=30.0, station_dz=5.0,
+                             station_stride=4, station_cap=200, laser_antenna=1, antenna_z_lab=25.0,
+                             antenna_t_peak=25.0)]
+    sa, sb = torch.cuda.Stream(), torch.cuda.Stream()
+    ref = [pic.Run(c, "fp32", stream=sa) for c in cfgs]
+    new = [pic.Run(c, "fp32", stream=sb) for c in cfgs]
+    for steps in ([20, 35, 40], [0, 6, 11]):
+        pic.pic_step_batch([r.handle for r in ref], steps)
+        pic.pic_step_batch_noalloc([r.handle for r in new], steps)
+        sa.synchronize()
+        sb.synchronize()
+        for a, b in zip(ref, new):
+            _same(a, b)
+        for q in range(3):
+            ta, fa, na = ref[2].station(q)
+            tb, fb, nb = new[2].station(q)
+            assert na == nb and np.array_equal(ta, tb) and np.array_equal(fa, fb), q
+    for r in ref + new:
+        r.close()
+
+
 def test_noalloc_batch_rejects_more_runs_than_the_table_holds():
     run = pic.Run(workloads.config("c1", nz=32, nx=16, ppc=1), "fp32")
     with pytest.raises(pic.PicError):
