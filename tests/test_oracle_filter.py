@@ -105,6 +105,37 @@ def test_open_z_end_repeats_the_end_value(ora):
     st.close()
 
 
+def _mirror_filter(a, n, comp):
+    """n binomial passes (then the compensating one) on the even extension of
+    a column about both of its end faces (period 2 len(a)), as periodic
+    convolutions."""
+    ext = np.concatenate([a, a[::-1]])
+    for p in range(n + comp):
+        ws, wm = (0.25, 0.5) if p < n else (-0.25 * n, 1.0 + 0.5 * n)
+        ext = wm * ext + ws * (np.roll(ext, 1) + np.roll(ext, -1))
+    return ext[: a.size]
+
+
+@pytest.mark.parametrize("nz,n,comp", [(32, 2, 1), (8, 12, 1), (8, 3, 0)])
+def test_open_end_rule_is_the_mirror_extension(ora, nz, n, comp):
+    """Repeating the end value at every pass is the same as filtering the
+    column's mirror image about its end faces with the periodic stencil, for
+    any number of passes (more passes than points included): a pass keeps
+    mirrored data mirrored and at the end point it reads the end value
+    itself.  Points beyond the range stay 0."""
+    st, cfg = _empty(ora, 2, nz=nz, bc_z="open", filter_passes=n, filter_compensate=comp)
+    rng = np.random.default_rng(nz + 7 * n)
+    az = rng.normal(size=nz)          # half points 0..nz-1
+    ax = rng.normal(size=nz + 1)      # nodes 0..nz
+    st.field(ora.JZ)[0, :, :nz] = az[None, :]   # constant across x: the x passes keep it
+    st.field(ora.JX)[0, :, : nz + 1] = ax[None, :]
+    st.filter_current()
+    np.testing.assert_allclose(st.field(ora.JZ)[0, 3, :nz], _mirror_filter(az, n, comp), rtol=0, atol=1e-12)
+    np.testing.assert_allclose(st.field(ora.JX)[0, 3, : nz + 1], _mirror_filter(ax, n, comp), rtol=0, atol=1e-12)
+    assert np.all(st.field(ora.JZ)[0, :, nz:] == 0.0)
+    st.close()
+
+
 def test_uniform_current_passes_an_open_end_unchanged(ora):
     """The drifting plasma's current is uniform up to both open ends: every
     pass, the compensating one included, leaves it as it is, so the filtered
