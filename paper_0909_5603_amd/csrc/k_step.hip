@@ -454,6 +454,36 @@ __device__ __forceinline__ void win_decode(const TileGeo<DIM>& g, int q, int& rz
   rx = t - ry * g.Wd[1];
 }
 
+// Tiles of the particle kernel dealt to the XCDs (workgroup b runs on XCD
+// b % 8) in blocks of 64 consecutive tiles, round-robin: block q goes to XCD
+// q % 8.  At 8 cells per tile a block is a row of tiles along z of a 512-cell
+// box, so each XCD's share covers the whole transverse plane and the busier
+// tiles near the laser axis (more crossings and bank conflicts once the wake
+// forms) are spread over all XCDs instead of the two that hold the central
+// slabs of a contiguous split; the XCDs working at the same time on
+// neighbouring rows still share their halo reads in the last-level cache.
+// Batches of fewer than 2048 tiles use smaller blocks (down to one tile),
+// at least 32 of them, so that every XCD gets several.  The workgroups of an XCD step through its
+// sequence of tiles together: workgroup j takes positions j, j + G/8, ...
+struct XcdDeal {
+  long long beg, end, stride, x;
+  int sh;
+  __device__ explicit XcdDeal(long long total) {
+    x = blockIdx.x & 7;
+    sh = 0;
+    while (sh < 6 && (total >> (sh + 1)) >= 32) ++sh;
+    const long long nb = (total + (1LL << sh) - 1) >> sh;
+    const long long cx = nb > x ? (nb - 1 - x) / 8 + 1 : 0;  // blocks x, x + 8, ...
+    long long len = cx << sh;
+    if (cx > 0 && x + 8 * (cx - 1) == nb - 1) len -= (nb << sh) - total;  // the last block is short
+    beg = blockIdx.x >> 3;
+    end = len;
+    stride = (long long)(gridDim.x >> 3);
+  }
+  // the tile at position k of this XCD's sequence
+  __device__ long long tile(long long k) const { return ((x + 8 * (k >> sh)) << sh) + (k & ((1LL << sh) - 1)); }
+};
+
 template <int DIM, typename R>
 __device__ __forceinline__ void tile_geo(const BatchTable* __restrict__ bt, long long w, TileGeo<DIM>& g) {
   using T = Tile<DIM, R>;
@@ -607,13 +637,13 @@ void k_particles(const BatchTable* __restrict__ bt) {
   auto& sF = sm.F;
   const int lane = threadIdx.x & 63;
 
-  const XcdSplit xs(bt->tiles);
+  const XcdDeal xs(bt->tiles);
   TileGeo<DIM> g;
   R ld[NU][6];
   int sidx[NU];
   unsigned zf[NU];
   if (xs.beg < xs.end) {
-    tile_geo<DIM, R>(bt, xs.beg, g);
+    tile_geo<DIM, R>(bt, xs.tile(xs.beg), g);
     if (g.p0 < g.p1) window_load<DIM, R, BLOCK, NU>(bt, g, ld, sidx, zf);
   }
   for (int q = threadIdx.x; q < 3 * WV; q += BLOCK) (&sJ[0][0])[q] = 0;
@@ -633,7 +663,7 @@ void k_particles(const BatchTable* __restrict__ bt) {
         bbw[3] = bbw[4] = bbw[5] = -(1 << 20);
       }
       if (wn < xs.end) {
-        tile_geo<DIM, R>(bt, wn, g);
+        tile_geo<DIM, R>(bt, xs.tile(wn), g);
         if (g.p0 < g.p1) window_load<DIM, R, BLOCK, NU>(bt, g, ld, sidx, zf);
       }
       continue;
@@ -820,7 +850,7 @@ void k_particles(const BatchTable* __restrict__ bt) {
     TileGeo<DIM> gn;
     gn.p0 = gn.p1 = 0;
     if (wn < xs.end) {
-      tile_geo<DIM, R>(bt, wn, gn);
+      tile_geo<DIM, R>(bt, xs.tile(wn), gn);
       if (gn.p0 < gn.p1) window_load<DIM, R, BLOCK, NU>(bt, gn, ld, sidx, zf);
     }
     if (bad) g_or(&rd.ctr->err, 1u);
