@@ -115,21 +115,26 @@ __device__ __forceinline__ int sort_key(RunC& rd, int cc, bool act, bool& whole)
 }
 
 // The work items of the runs that sort at this step, as one flat range:
-// thread t reads run t's counters (in parallel), the workgroup scans the
-// item counts in LDS, and item w maps back to its run by a binary search of
-// the scan.  A step where no run sorts (most steps) costs one round of loads;
-// a step where one small run of a large batch sorts touches only its items.
-// Every thread of the workgroup must call it; returns the number of items.
+// thread t reads run t's counters (in parallel) and counts that run's live
+// items with count(rd) (the particles it creates, or the slots it holds, in
+// chunks), the workgroup scans the counts in LDS, and item w maps back to
+// its run by a binary search of the scan.  Counting live items, not the
+// run's largest possible number, keeps every XCD busy: a cadence injection
+// creates a few columns of a box sized for all of them, and its items would
+// otherwise all fall in the first XCD's share of the range.  A step where no
+// run sorts (most steps) costs one round of loads; a step where one small run
+// of a large batch sorts touches only its items.  Every thread of the
+// workgroup must call it; returns the number of items.
 struct SortItems {
   long long pre[MAX_BATCH + 1];
 };
 
-__device__ __forceinline__ long long sort_items(const BatchTable* bt, const long long* pre_items,
-                                                SortItems& si) {
+template <typename Count>
+__device__ __forceinline__ long long sort_items(const BatchTable* bt, SortItems& si, Count count) {
   const int n = bt->n;
   for (int r = threadIdx.x; r < n; r += blockDim.x) {
     RunC& rd = *bt->run[r];
-    si.pre[r + 1] = sort_due(*rd.ctr, rd.inject_every) ? pre_items[r + 1] - pre_items[r] : 0;
+    si.pre[r + 1] = sort_due(*rd.ctr, rd.inject_every) ? count(rd) : 0;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -142,6 +147,20 @@ __device__ __forceinline__ long long sort_items(const BatchTable* bt, const long
   }
   __syncthreads();
   return si.pre[n];
+}
+
+// live items of a run that sorts: chunks of the particles it creates, and
+// chunks of its slots (the current ones and the created ones)
+__device__ __forceinline__ long long inject_items(RunC& rd) {
+  long long kend, nnew;
+  pending(rd, *rd.ctr, kend, nnew);
+  return (nnew + INJ_CHUNK - 1) / INJ_CHUNK;
+}
+__device__ __forceinline__ long long slot_items(RunC& rd) {
+  long long kend, nnew;
+  pending(rd, *rd.ctr, kend, nnew);
+  const long long total = min(rd.ctr->n_slots + nnew, rd.capacity);
+  return (total + PART_CHUNK - 1) / PART_CHUNK;
 }
 
 // the run of sorting item w: the last r with pre[r] <= w
@@ -174,7 +193,7 @@ __device__ __forceinline__ void blocked_cell(unsigned b, int nx, int ny, int tx,
 template <typename R>
 __global__ __launch_bounds__(256) void k_inject(const BatchTable* __restrict__ bt) {
   __shared__ SortItems si;
-  const long long items = sort_items(bt, bt->pre_injblk, si);
+  const long long items = sort_items(bt, si, inject_items);
   if (items == 0) return;
   const XcdSplit xs(items);
   for (long long w = xs.beg; w < xs.end; w += xs.stride) {
@@ -288,7 +307,7 @@ template <int DIM, typename R>
 __global__ __launch_bounds__(256) void k_count(const BatchTable* __restrict__ bt) {
   __shared__ SortItems si;
   __shared__ int hkey[COUNT_HASH], hcnt[COUNT_HASH], hfull[COUNT_HASH];
-  const long long items = sort_items(bt, bt->pre_partblk, si);
+  const long long items = sort_items(bt, si, slot_items);
   if (items == 0) return;
   const int lane = threadIdx.x & 63;
   const XcdSplit xs(items);
@@ -436,7 +455,7 @@ __global__ __launch_bounds__(1024) void k_scan(const BatchTable* __restrict__ bt
 template <int DIM, typename R>
 __global__ __launch_bounds__(256) void k_scatter(const BatchTable* __restrict__ bt) {
   __shared__ SortItems si;
-  const long long items = sort_items(bt, bt->pre_partblk, si);
+  const long long items = sort_items(bt, si, slot_items);
   if (items == 0) return;
   const XcdSplit xs(items);
   for (long long w = xs.beg; w < xs.end; w += xs.stride) {
@@ -498,7 +517,7 @@ __global__ __launch_bounds__(256) void k_scatter(const BatchTable* __restrict__ 
 // the runs that sort).
 __global__ __launch_bounds__(256) void k_full_reset(const BatchTable* __restrict__ bt) {
   __shared__ SortItems si;
-  const long long items = sort_items(bt, bt->pre_tiles, si);
+  const long long items = sort_items(bt, si, [](RunC& rd) { return (long long)rd.ntiles; });
   if (items == 0) return;
   for (long long w = (long long)blockIdx.x * 256 + threadIdx.x; w < items; w += (long long)gridDim.x * 256) {
     const int r = sort_item_run(si, bt->n, w);
