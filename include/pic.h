@@ -217,7 +217,7 @@ pic_status pic_step_batch(pic_run* const* runs, const int* nsteps, int n);
  * tight serving loops, harnesses that forbid allocation): the same steps as
  * pic_step_batch, with the same arguments, rules and results, but the batch
  * table the kernels read lives in a device array of the library (one table,
- * sizeof(BatchTable) = 10 KiB, per GPU, kept until the process ends; the
+ * sizeof(BatchTable) = 6 KiB, per GPU, kept until the process ends; the
  * current device's is used, and set up on the first call there) and the
  * steps are launched directly, so the call allocates no device or pinned
  * host memory and creates no graph or event.  Limit: n <= 256 runs

@@ -293,23 +293,17 @@ T* at(pic_run* r, size_t off) {
 void fill_table(BatchTable& t, pic_run* const* runs, int n) {
   memset(&t, 0, sizeof(t));
   t.n = n;
-  long long a = 0, b = 0, c = 0, e = 0;
+  long long a = 0, b = 0;
   for (int i = 0; i < n; ++i) {
     const Derived& d = runs[i]->d;
     t.run[i] = runs[i]->drd;
     t.pre_tiles[i] = a;
     t.pre_cellblk[i] = b;
-    t.pre_partblk[i] = c;
-    t.pre_injblk[i] = e;
     a += d.ntiles;
     b += (d.npts + CELL_BLOCK - 1) / CELL_BLOCK;
-    c += (d.capacity + PART_CHUNK - 1) / PART_CHUNK;
-    e += (d.max_new + INJ_CHUNK - 1) / INJ_CHUNK;
   }
   t.pre_tiles[n] = t.tiles = a;
   t.pre_cellblk[n] = t.cellblk = b;
-  t.pre_partblk[n] = t.partblk = c;
-  t.pre_injblk[n] = t.injblk = e;
 }
 
 void host_advance(pic_run* r) { ++r->hstep; }

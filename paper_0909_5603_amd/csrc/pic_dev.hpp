@@ -168,18 +168,17 @@ struct RunDev {
 // a run descriptor as the kernels see it (read-only, constant address space)
 using RunC = const PIC_C RunDev;
 
-// A set of runs advanced by the same launches.  Work items of every kernel
-// are enumerated run by run; pre_* are exclusive prefix sums of the per-run
-// item counts.
+// A set of runs advanced by the same launches.  Work items of the step's
+// kernels are enumerated run by run; pre_* are exclusive prefix sums of the
+// per-run item counts (tiles, field blocks).  The sort kernels count the
+// live items of each run when they start.
 struct BatchTable {
   int n;
   int pad;
-  long long tiles, cellblk, partblk, injblk;
+  long long tiles, cellblk;
   RunC* run[MAX_BATCH];
   long long pre_tiles[MAX_BATCH + 1];
   long long pre_cellblk[MAX_BATCH + 1];
-  long long pre_partblk[MAX_BATCH + 1];
-  long long pre_injblk[MAX_BATCH + 1];
 };
 
 constexpr int CELL_BLOCK = 256;     // cells per field work item
