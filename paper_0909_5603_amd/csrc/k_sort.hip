@@ -102,15 +102,26 @@ __device__ __forceinline__ int sort_key(RunC& rd, int cc, bool act, bool& whole)
   const int own = act ? tile_of<DIM, R>(rd, cc) : 0;
   whole = false;
   if (__ballot(act) != ~0ull) return own;
-  int kmin = cell_k(cc), kmax = kmin;
+  // the z range of the group from ballots of the lanes' offsets to lane 0's
+  // cell (uniform values, no cross-lane shuffles): it spans at most GZ + 1
+  // cells iff every lane lies within GZ of lane 0 and the lowest and
+  // highest offsets present are at most GZ apart
+  const int k = cell_k(cc), k0 = __builtin_amdgcn_readfirstlane(k);
+  unsigned long long seen = 0;
+  int lo = T::GZ + 1, hi = -T::GZ - 1;
 #pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) {
-    kmin = min(kmin, __shfl_xor(kmin, m));
-    kmax = max(kmax, __shfl_xor(kmax, m));
+  for (int d = -T::GZ; d <= T::GZ; ++d) {
+    const unsigned long long b = __ballot(k - k0 == d);
+    if (b) {
+      lo = min(lo, d);
+      hi = max(hi, d);
+      seen |= b;
+    }
   }
-  if (kmax - kmin > T::GZ) return own;
-  const int key = own - ((cell_k(cc) >> T::LZ) - (kmin >> T::LZ));  // tiles are z-fastest
-  whole = __ballot(key == __shfl(key, 0)) == ~0ull;
+  if (seen != ~0ull || hi - lo > T::GZ) return own;
+  const int kmin = k0 + lo;
+  const int key = own - ((k >> T::LZ) - (kmin >> T::LZ));  // tiles are z-fastest
+  whole = __ballot(key == __builtin_amdgcn_readfirstlane(key)) == ~0ull;
   return whole ? key : own;
 }
 
