@@ -214,25 +214,26 @@ def test_batched_runs_equal_alone():
         r.close()
 
 
-def test_batched_3d_runs_equal_alone_bitwise():
-    """Split-precision 3D runs advanced in one batch equal each run advanced
-    alone bit for bit (currents are integer sums, so the order in which
-    tiles and particles are visited cannot show), through a cadence sort
-    with injection.  The batch holds more than 2048 tiles, not a multiple
-    of 64, so the particle kernel deals its tiles to the XCDs in full
-    64-tile blocks and a short last one; the runs drift at different
-    speeds, so the sort's work items differ from run to run."""
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_batched_3d_runs_equal_alone_bitwise(prec):
+    """3D runs advanced in one batch equal each run advanced alone bit for
+    bit (currents are integer sums, so the order in which tiles and
+    particles are visited cannot show), through a cadence sort with
+    injection.  The batch holds more than 2048 tiles, not a multiple of 64,
+    so the particle kernel deals its tiles to the XCDs in full 64-tile
+    blocks and a short last one; the runs drift at different speeds, so the
+    sort's work items differ from run to run."""
     cfgs = [workloads.config("c5", nz=128, nx=64, ny=64, ppc=2, seed=21),
             workloads.config("c5", nz=136, nx=64, ny=72, ppc=2, gamma_boost=13.0, a0=1.0, seed=22),
             workloads.config("c5", nz=20, nx=24, ny=16, ppc=3, gamma_boost=5.0, a0=0.0, seed=23)]
     steps = [23, 21, 22]  # each crosses the cadence sort at step 20
     alone = []
     for c, s in zip(cfgs, steps):
-        r = pic.Run(c, "fp32")
+        r = pic.Run(c, prec)
         r.step(s)
         alone.append(r)
     shared = torch.cuda.Stream()
-    mixed = [pic.Run(c, "fp32", stream=shared) for c in cfgs]
+    mixed = [pic.Run(c, prec, stream=shared) for c in cfgs]
     tiles = sum(pic.pic_get_derived(r.handle)["ntiles"] for r in mixed)
     assert tiles > 2048 and tiles % 64 != 0, tiles
     pic.pic_step_batch([r.handle for r in mixed], steps)
