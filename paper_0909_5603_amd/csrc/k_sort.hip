@@ -341,6 +341,7 @@ __global__ __launch_bounds__(256) void k_count(const BatchTable* __restrict__ bt
     // n particles go to tile key (full: as a whole group)
     auto tally = [&](int key, int n, bool full) {
       int h = key & (COUNT_HASH - 1);
+#pragma nounroll
       for (int probe = 0; probe < COUNT_HASH; ++probe) {
         const int prev = atomicCAS(&hkey[h], -1, key);
         if (prev == -1 || prev == key) {
